@@ -1,0 +1,198 @@
+/*
+ * pauliprop -- Heisenberg-picture Pauli propagation on MI355X (gfx950).
+ *
+ * Computes <O>(theta) = <0...0| U(theta)^dag O U(theta) |0...0> for a
+ * parameterized circuit U = g_m ... g_1 (Sec. I: a PQC of m fixed and
+ * parameterized gates) by propagating the observable O, a real-weighted sum
+ * of n-qubit Pauli strings (Sec. II-A), backwards through the gates:
+ *   - a Clifford gate (H, S, CX) maps every string to one string with a sign
+ *     (Sec. II-A: constant-time local update; CX list of Sec. III-C;
+ *     H and S rows of Table I, applied as the inverse map g^dag P g);
+ *   - a rotation R_sigma(theta) = exp(-i theta sigma/2) keeps every string that
+ *     commutes with sigma and splits every anticommuting one into a cos(theta)
+ *     string and a sin(theta) string (R rows of Table I, Example 1);
+ *   - strings that coincide are merged by summing their weights, with no
+ *     pruning (Sec. III-B expand/reduce, eq. (7), Examples 3 and 4);
+ *   - <O> is the sum of the weights of the strings made of I and Z only.
+ *
+ * Conventions used by every entry point:
+ *   qubit q is bit q of the x and z words; I=(0,0) X=(1,0) Y=(1,1) Z=(0,1);
+ *   Y is the Hermitian Pauli; weights are real; gates are given in
+ *   application order g_1 ... g_m; rotations read their angle from
+ *   theta[param[g]].
+ *
+ * Errors: every function returns a pp_status; on failure pp_last_error()
+ * returns a thread-local message and the object is left as it was.
+ * Asynchrony: functions taking a stream enqueue work on that HIP stream
+ * (a hipStream_t passed as void*, NULL = the null stream) and return; device
+ * outputs are valid once the stream has reached that point.  Functions that
+ * return host data (pp_get_terms, pp_get_stats) synchronize the stream.
+ * Threading: one circuit must not be used by two threads at once; distinct
+ * circuits are independent.
+ */
+#ifndef PAULIPROP_H
+#define PAULIPROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define PP_API __attribute__((visibility("default")))
+#else
+#define PP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pp_status {
+    PP_OK = 0,
+    PP_ERR_INVALID = 1,  /* bad argument: the object is unchanged */
+    PP_ERR_NOMEM = 2,    /* device or host allocation failed */
+    PP_ERR_DEVICE = 3,   /* a HIP call failed (message kept) */
+    PP_ERR_CAPACITY = 4, /* the term set does not fit the configured capacity */
+    PP_ERR_STATE = 5,    /* call order: gates / theta / observable missing */
+    PP_ERR_BUSY = 6      /* server: no slot or memory free yet */
+} pp_status;
+
+/* Gate codes (Sec. III-A: an instructor is {gate, wire, theta}). */
+typedef enum pp_op { PP_H = 0, PP_S = 1, PP_CX = 2, PP_RX = 3, PP_RY = 4, PP_RZ = 5 } pp_op;
+
+/* Storage type of the weights.  Arithmetic inside a pass is FP64 in both. */
+typedef enum pp_dtype { PP_F64 = 0, PP_F32 = 1 } pp_dtype;
+
+/* Engine.
+ *  DENSE : direct addressing; the weight of string P lives at slot
+ *          index(P) of a 4^n array (the paper's lambda vector indexed
+ *          0 ... 4^n - 1, Sec. III-B), so merging duplicates is implicit.
+ *          Practical for n <= 13.
+ *  SPARSE: an explicit list of (x, z, weight) in struct-of-arrays form;
+ *          each pass applies a run of Clifford gates and one rotation,
+ *          appends the split strings by wave-ballot compaction, then merges
+ *          duplicates with a radix sort and a segmented FP64 sum.
+ *          n <= 64; the capacity is set with PP_OPT_MAX_TERMS.
+ *  AUTO  : DENSE when 4^n slots fit the memory budget, else SPARSE. */
+typedef enum pp_engine { PP_ENGINE_AUTO = 0, PP_ENGINE_DENSE = 1, PP_ENGINE_SPARSE = 2 } pp_engine;
+
+/* Per-circuit options (pp_circuit_set_option). */
+typedef enum pp_option {
+    PP_OPT_TRACK_TERMS = 0, /* 1: keep the exact string set and count term
+                               updates (needed by pp_get_terms in DENSE);
+                               0 (default): weights only, fastest */
+    PP_OPT_TILE_QUBITS = 1, /* DENSE, n >= 8: qubits per LDS tile (4..7);
+                               0 = autotuned default */
+    PP_OPT_MAX_TERMS = 2,   /* SPARSE: capacity of the term list (default
+                               min(4^n, 2^24)); the buffers hold 2x this */
+    PP_OPT_USE_GRAPH = 3,   /* 1: replay a captured hipGraph for evaluate */
+    PP_OPT_BLOCK = 4        /* threads per workgroup (64..1024), 0 = default */
+} pp_option;
+
+typedef struct pp_circuit pp_circuit;
+
+typedef struct pp_stats {
+    int64_t term_updates; /* U = sum over gates of the set size entering the
+                             gate, from the last tracked (or SPARSE) run */
+    int64_t final_terms;  /* strings in the final set (tracked or SPARSE) */
+    int64_t gates;        /* m */
+    int64_t ops;          /* device operations after fusion */
+    int64_t passes;       /* passes over the term set per evaluation */
+    int64_t launches;     /* kernel launches per evaluation */
+    int64_t bytes_per_eval; /* algorithmic HBM bytes of one evaluation */
+    int32_t engine;       /* pp_engine actually used */
+    int32_t tile_qubits;  /* DENSE: qubits per tile (n if LDS-resident) */
+    int32_t overflow;     /* SPARSE: 1 if the capacity was exceeded */
+    int32_t reserved;
+} pp_stats;
+
+/* Accumulated device time of one kernel class (pp_profile_read). */
+typedef struct pp_kernel_time {
+    char name[32];      /* "tile_pass", "resident", "compose", "dense_init",
+                           "readout", "sparse_pass", "sparse_merge" */
+    int64_t launches;   /* launches timed since profiling was enabled */
+    double total_ms;    /* sum of event-measured durations */
+} pp_kernel_time;
+
+/* Library version string; never NULL. */
+PP_API const char *pp_version(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+PP_API const char *pp_last_error(void);
+
+/* Creates an empty circuit on the current HIP device.  n_qubits in [1, 64]
+ * (DENSE additionally needs 4^n slots in memory).  *out receives the handle;
+ * release it with pp_circuit_destroy. */
+PP_API pp_status pp_circuit_create(int32_t n_qubits, pp_dtype dtype, pp_engine engine, pp_circuit **out);
+
+/* Releases the circuit and every device buffer it owns.  NULL-safe.  The
+ * caller must make sure no enqueued work still uses it. */
+PP_API void pp_circuit_destroy(pp_circuit *c);
+
+/* Loads the gate list (host arrays of length m, copied during the call).
+ * op[g] is a pp_op; q0[g] the qubit (CX control); q1[g] the CX target, else
+ * ignored; param[g] in [0, n_params) for rotations, ignored otherwise.
+ * Errors: PP_ERR_INVALID for an unknown op, a qubit outside [0, n),
+ * CX with q0 == q1 or a parameter index outside [0, n_params). */
+PP_API pp_status pp_circuit_load_gates(pp_circuit *c, int64_t m, const uint8_t *op, const int32_t *q0,
+                                const int32_t *q1, const int32_t *param, int32_t n_params);
+
+/* Sets the n_params angles.  on_device = 0: theta is a host array (copied
+ * before return); 1: theta is a device array read by the next evaluations
+ * on `stream` (it must stay valid until they ran).  Non-finite angles are
+ * not checked; they propagate NaN. */
+PP_API pp_status pp_circuit_set_theta(pp_circuit *c, const double *theta, int32_t on_device, void *stream);
+
+/* Sets the observable O = sum_k coeff[k] P(x[k], z[k]) (host arrays, copied).
+ * Bits at or above n must be zero.  Repeated strings are summed. */
+PP_API pp_status pp_circuit_set_observable(pp_circuit *c, int64_t n_terms, const uint64_t *x,
+                                    const uint64_t *z, const double *coeff);
+
+/* Sets a pp_option; takes effect at the next evaluation. */
+PP_API pp_status pp_circuit_set_option(pp_circuit *c, pp_option key, int64_t value);
+
+/* Enqueues one evaluation of <O>; d_expval is caller-owned device memory for
+ * one double.  PP_ERR_STATE if gates, theta or the observable are missing. */
+PP_API pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval);
+
+/* Evaluates `count` independent circuits in batched launches on `stream`:
+ * circuits that fit one workgroup's LDS run one per workgroup in a single
+ * launch per size class, larger ones share multi-circuit tiled passes.
+ * d_expvals: caller-owned device array of `count` doubles, in input order.
+ * Each circuit's result is bit-identical to its own pp_evaluate. */
+PP_API pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, void *stream, double *d_expvals);
+
+/* Enqueues <O> and its gradient with respect to theta (adjoint method on the
+ * DENSE engine): d_expval one double, d_grad n_params doubles (caller-owned
+ * device memory; contributions of gates sharing a parameter are summed).
+ * checkpoint_every_gates > 0 stores the propagated set every that many gates
+ * and recomputes inside each segment; 0 picks a default. */
+PP_API pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_every_gates, double *d_expval,
+                      double *d_grad);
+
+/* Copies the final string set of the last evaluation to host arrays in
+ * canonical order (by z, then x), synchronizing `stream`.  DENSE requires
+ * PP_OPT_TRACK_TERMS = 1 for that evaluation.  At most `capacity` strings are
+ * written; *n_out receives the full count (PP_ERR_CAPACITY if larger). */
+PP_API pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *x, uint64_t *z,
+                       double *coeff, int64_t *n_out);
+
+/* Fills *out with the statistics of the last evaluation (synchronizes the
+ * stream of that evaluation). */
+PP_API pp_status pp_get_stats(pp_circuit *c, pp_stats *out);
+
+/* Kernel timing for measurement: while enabled (on = 1), every kernel launch
+ * of the library is bracketed by a pair of HIP events recorded on the stream
+ * it is launched on.  on = 0 stops recording.  Not thread-safe; meant for
+ * benchmarks. */
+PP_API pp_status pp_profile_enable(int32_t on);
+
+/* Synchronizes on the recorded events and writes up to `max` per-class
+ * totals (launches and summed milliseconds) into out[], *n_out = classes
+ * written; then clears the record. */
+PP_API pp_status pp_profile_read(pp_kernel_time *out, int32_t max, int32_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAULIPROP_H */

@@ -1,0 +1,93 @@
+"""ctypes loader for libpauliprop.so (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpauliprop.so")
+
+PP_OK, PP_ERR_INVALID, PP_ERR_NOMEM, PP_ERR_DEVICE, PP_ERR_CAPACITY, PP_ERR_STATE, PP_ERR_BUSY = range(7)
+STATUS_NAMES = ["PP_OK", "PP_ERR_INVALID", "PP_ERR_NOMEM", "PP_ERR_DEVICE", "PP_ERR_CAPACITY",
+                "PP_ERR_STATE", "PP_ERR_BUSY"]
+PP_F64, PP_F32 = 0, 1
+PP_ENGINE_AUTO, PP_ENGINE_DENSE, PP_ENGINE_SPARSE = 0, 1, 2
+PP_OPT_TRACK_TERMS, PP_OPT_TILE_QUBITS, PP_OPT_MAX_TERMS, PP_OPT_USE_GRAPH, PP_OPT_BLOCK = range(5)
+
+
+class PPStats(ctypes.Structure):
+    _fields_ = [("term_updates", ctypes.c_int64), ("final_terms", ctypes.c_int64),
+                ("gates", ctypes.c_int64), ("ops", ctypes.c_int64), ("passes", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("bytes_per_eval", ctypes.c_int64),
+                ("engine", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
+                ("overflow", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class PPKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class PauliPropError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {message}")
+
+
+_lib = None
+
+
+def load():
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python __graft_entry__.py` "
+                           "(or paper_2502_10685_amd/build.py); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    st = ctypes.c_int
+    sigs = {
+        "pp_version": (ctypes.c_char_p, []),
+        "pp_last_error": (ctypes.c_char_p, []),
+        "pp_circuit_create": (st, [I32, ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)]),
+        "pp_circuit_destroy": (None, [P]),
+        "pp_circuit_load_gates": (st, [P, I64, P, P, P, P, I32]),
+        "pp_circuit_set_theta": (st, [P, P, I32, P]),
+        "pp_circuit_set_observable": (st, [P, I64, P, P, P]),
+        "pp_circuit_set_option": (st, [P, ctypes.c_int, I64]),
+        "pp_evaluate": (st, [P, P, P]),
+        "pp_evaluate_batch": (st, [P, I64, P, P]),
+        "pp_gradient": (st, [P, P, I32, P, P]),
+        "pp_get_terms": (st, [P, P, I64, P, P, P, ctypes.POINTER(I64)]),
+        "pp_get_stats": (st, [P, ctypes.POINTER(PPStats)]),
+        "pp_profile_enable": (st, [I32]),
+        "pp_profile_read": (st, [ctypes.POINTER(PPKernelTime), I32, ctypes.POINTER(I32)]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != PP_OK:
+        msg = load().pp_last_error().decode(errors="replace")
+        raise PauliPropError(status, msg)
+
+
+def profile_enable(on=True):
+    check(load().pp_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """{kernel class: (launches, total_ms)} since the last read."""
+    buf = (PPKernelTime * 16)()
+    n = ctypes.c_int32(0)
+    check(load().pp_profile_read(buf, 16, ctypes.byref(n)))
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}

@@ -1,0 +1,170 @@
+"""Python binding of libpauliprop: device memory and streams come from torch;
+every step of the propagation runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DTYPES = {"f64": L.PP_F64, "fp64": L.PP_F64, "float64": L.PP_F64,
+           "f32": L.PP_F32, "fp32": L.PP_F32, "float32": L.PP_F32}
+_ENGINES = {"auto": L.PP_ENGINE_AUTO, "dense": L.PP_ENGINE_DENSE, "sparse": L.PP_ENGINE_SPARSE}
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("pauliprop needs a HIP device (MI355X); none is visible")
+
+
+class Circuit:
+    """One parameterized circuit with an observable, owned by the library."""
+
+    def __init__(self, n, op, q0, q1, param, n_params, obs_x, obs_z, obs_c, *, theta=None,
+                 dtype="f64", engine="auto", track=False, tile_qubits=0, use_graph=False,
+                 max_terms=0):
+        _require_gpu()
+        self._lib = L.load()
+        self.n = int(n)
+        self.n_params = int(n_params)
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        L.check(self._lib.pp_circuit_create(self.n, _DTYPES[dtype], _ENGINES[engine], ctypes.byref(h)))
+        self._h = h
+        self.load_gates(op, q0, q1, param, n_params)
+        self.set_observable(obs_x, obs_z, obs_c)
+        if track:
+            self.set_option(L.PP_OPT_TRACK_TERMS, 1)
+        if tile_qubits:
+            self.set_option(L.PP_OPT_TILE_QUBITS, tile_qubits)
+        if use_graph:
+            self.set_option(L.PP_OPT_USE_GRAPH, 1)
+        if max_terms:
+            self.set_option(L.PP_OPT_MAX_TERMS, max_terms)
+        if theta is not None:
+            self.set_theta(theta)
+
+    @classmethod
+    def from_workload(cls, wc, **kw):
+        return cls(wc.n, wc.op, wc.q0, wc.q1, wc.param, wc.n_params, wc.obs_x, wc.obs_z, wc.obs_c,
+                   theta=wc.theta, **kw)
+
+    # -------------------------------------------------------------- setup
+    def load_gates(self, op, q0, q1, param, n_params):
+        op = np.ascontiguousarray(op, dtype=np.uint8)
+        q0 = np.ascontiguousarray(q0, dtype=np.int32)
+        q1 = np.ascontiguousarray(q1, dtype=np.int32)
+        param = np.ascontiguousarray(param, dtype=np.int32)
+        self.m = int(op.shape[0])
+        L.check(self._lib.pp_circuit_load_gates(self._h, self.m, _ptr(op), _ptr(q0), _ptr(q1),
+                                                _ptr(param), int(n_params)))
+        self.n_params = int(n_params)
+
+    def set_observable(self, x, z, c):
+        x = np.ascontiguousarray(x, dtype=np.uint64)
+        z = np.ascontiguousarray(z, dtype=np.uint64)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        L.check(self._lib.pp_circuit_set_observable(self._h, int(x.shape[0]), _ptr(x), _ptr(z), _ptr(c)))
+
+    def set_theta(self, theta, stream=None):
+        if isinstance(theta, torch.Tensor) and theta.is_cuda:
+            t = theta.detach().to(torch.float64).contiguous()
+            L.check(self._lib.pp_circuit_set_theta(self._h, ctypes.c_void_p(t.data_ptr()), 1,
+                                                   _stream(stream)))
+            self._theta_keep = t
+        else:
+            a = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+            if a.size == 0:
+                a = np.zeros(1)
+            L.check(self._lib.pp_circuit_set_theta(self._h, _ptr(a), 0, _stream(stream)))
+
+    def set_option(self, key, value):
+        L.check(self._lib.pp_circuit_set_option(self._h, int(key), int(value)))
+
+    # ---------------------------------------------------------- evaluation
+    def evaluate(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device="cuda")
+        L.check(self._lib.pp_evaluate(self._h, _stream(stream), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def gradient(self, checkpoint_every=0, stream=None):
+        ev = torch.empty((), dtype=torch.float64, device="cuda")
+        grad = torch.zeros(max(self.n_params, 1), dtype=torch.float64, device="cuda")
+        L.check(self._lib.pp_gradient(self._h, _stream(stream), int(checkpoint_every),
+                                      ctypes.c_void_p(ev.data_ptr()), ctypes.c_void_p(grad.data_ptr())))
+        return ev, grad[: self.n_params]
+
+    def terms(self, capacity=None, stream=None):
+        """Final string set of the last evaluation, canonical order (z, then x)."""
+        if capacity is None:
+            capacity = min(4 ** self.n, 1 << 26)
+        x = np.zeros(capacity, np.uint64)
+        z = np.zeros(capacity, np.uint64)
+        c = np.zeros(capacity, np.float64)
+        nout = ctypes.c_int64(0)
+        L.check(self._lib.pp_get_terms(self._h, _stream(stream), capacity, _ptr(x), _ptr(z), _ptr(c),
+                                       ctypes.byref(nout)))
+        k = nout.value
+        return x[:k], z[:k], c[:k]
+
+    def stats(self) -> dict:
+        s = L.PPStats()
+        L.check(self._lib.pp_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pp_circuit_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def evaluate_batch(circuits, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    lib = L.load()
+    n = len(circuits)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+    arr = (ctypes.c_void_p * max(n, 1))(*[c._h.value for c in circuits])
+    L.check(lib.pp_evaluate_batch(ctypes.cast(arr, ctypes.c_void_p), n, _stream(stream),
+                                  ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+class _ExpvalFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, circ, checkpoint_every):
+        circ.set_theta(theta)
+        if theta.requires_grad:
+            ev, grad = circ.gradient(checkpoint_every)
+            ctx.save_for_backward(grad)
+        else:
+            ev = circ.evaluate()
+            ctx.save_for_backward(torch.zeros(0, dtype=torch.float64, device=ev.device))
+        return ev.clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (grad,) = ctx.saved_tensors
+        return (grad_out * grad).to(grad.dtype), None, None
+
+
+def expval(circ: Circuit, theta: torch.Tensor, checkpoint_every: int = 0) -> torch.Tensor:
+    """<O>(theta) with an adjoint gradient behind torch.autograd."""
+    return _ExpvalFn.apply(theta, circ, checkpoint_every)

@@ -1,0 +1,1008 @@
+// C ABI of libpauliprop (declared in include/pauliprop.h).
+//
+// A pp_circuit owns its gate list, angles, observable, the cached schedule
+// (rebuilt only when the gates or a schedule option change, never for new
+// angles) and its device buffers.  Every step of an evaluation runs in the
+// kernels of dense.hip / sparse.hip; this file only plans, allocates and
+// enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pauliprop.h"
+#include "plan.h"
+#include "pp_device.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pp_status fail(pp_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? PP_ERR_NOMEM : PP_ERR_DEVICE,         \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    return hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+template <class T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+__global__ void copy_f64_kernel(const double *src, double *dst, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = src[i];
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+__global__ void compact_to_sparse_count_kernel(const unsigned long long *total, long long *count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        count[0] = (long long)*total;
+        count[1] = 0;
+    }
+}
+
+constexpr int kResidentMaxN = 7;
+constexpr int kDenseMaxN = 16;
+constexpr int kAutoDenseMaxN = 13;
+constexpr int kLowQubits = 2;
+
+int default_tile_qubits(int n) { return n >= 10 ? 6 : 5; }
+
+// pinned staging for small asynchronous uploads, reused once the previous
+// upload from it has completed
+struct Staging {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    pp_status reserve(size_t bytes) {
+        if (done) HIPCHK(hipEventSynchronize(done));
+        if (bytes <= cap) return PP_OK;
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+        cap = 0;
+        HIPCHK(hipHostMalloc(&host, std::max<size_t>(bytes, 4096), hipHostMallocDefault));
+        cap = std::max<size_t>(bytes, 4096);
+        return PP_OK;
+    }
+    pp_status upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
+        pp_status r = reserve(bytes);
+        if (r != PP_OK) return r;
+        std::memcpy(host, src, bytes);
+        HIPCHK(hipMemcpyAsync(dst, host, bytes, hipMemcpyHostToDevice, s));
+        if (!done) HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(done, s));
+        return PP_OK;
+    }
+    void release() {
+        if (done) (void)hipEventSynchronize(done);
+        if (done) (void)hipEventDestroy(done);
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+        done = nullptr;
+        cap = 0;
+    }
+};
+
+// ----------------------------------------------------------- kernel timing
+enum ProfClass { PC_TILE = 0, PC_RES, PC_COMPOSE, PC_INIT, PC_READOUT, PC_SPASS, PC_SMERGE, PC_N };
+const char *const kProfNames[PC_N] = {"tile_pass", "resident",  "compose",     "dense_init",
+                                      "readout",   "sparse_pass", "sparse_merge"};
+
+struct Prof {
+    bool on = false;
+    int capturing = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> recs;  // class, index of the start event
+    hipEvent_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+};
+Prof g_prof;
+
+// Brackets the launches made during its lifetime with two events.
+struct ProfScope {
+    int cls;
+    hipStream_t s;
+    size_t idx = 0;
+    bool active;
+    ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+        active = g_prof.on && !g_prof.capturing;
+        if (!active) return;
+        idx = g_prof.used;
+        hipEvent_t a = g_prof.take(), b = g_prof.take();
+        active = a && b && hipEventRecord(a, s) == hipSuccess;
+    }
+    ~ProfScope() {
+        if (!active) return;
+        if (hipEventRecord(g_prof.pool[idx + 1], s) == hipSuccess) g_prof.recs.push_back({cls, idx});
+    }
+};
+
+}  // namespace
+
+struct pp_circuit {
+    int n = 0;
+    pp_dtype dtype = PP_F64;
+    pp_engine req = PP_ENGINE_AUTO;
+    int engine = PP_ENGINE_DENSE;
+    int dbytes = 8;
+
+    pp::GateList g;
+    bool have_gates = false;
+    double *d_theta = nullptr;
+    int theta_cap = 0;
+    bool have_theta = false;
+    std::vector<uint64_t> ox, oz;
+    std::vector<double> oc;
+    bool have_obs = false;
+    uint64_t *d_ox = nullptr, *d_oz = nullptr;
+    double *d_oc = nullptr;
+
+    int track = 0, tile_opt = 0, use_graph = 0, block = 0;
+    int64_t max_terms = 0;
+
+    // schedule cache
+    bool plan_valid = false;
+    int plan_track = -1, plan_k = -1;
+    uint64_t plan_gen = 0;  // bumped whenever device descriptors change
+    pp::DensePlan dplan;
+    pp::SparsePlan splan;
+
+    // dense buffers
+    void *coef = nullptr;
+    uint8_t *pres = nullptr;
+    pp::DOp *d_ops = nullptr;
+    double *d_maps = nullptr;
+    int32_t *d_roff = nullptr, *d_rparam = nullptr;
+    uint8_t *d_rop = nullptr;
+    pp::TilePassDesc *d_pass = nullptr;
+    pp::ResidentDesc *d_res = nullptr;
+    pp::ComposeDesc *d_comp = nullptr;
+    pp::ResidentDesc h_res{};
+    pp::ComposeDesc h_comp{};
+    std::vector<pp::TilePassDesc> h_pass;
+    unsigned long long *d_counters = nullptr;
+    double *d_result = nullptr;
+
+    // sparse buffers
+    pp::SparseBuffers sb{};
+    void *sb_base[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    uint32_t *d_codes = nullptr;
+    double *d_partials = nullptr;
+
+    // graph of one evaluation (tiled dense path)
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+
+    Staging staging;
+    pp_stats st{};
+    bool evaluated = false;
+    int last_track = 0;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+void free_graph(pp_circuit *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+void free_plan_buffers(pp_circuit *c) {
+    free_graph(c);
+    dfree(c->d_ops);
+    dfree(c->d_maps);
+    dfree(c->d_roff);
+    dfree(c->d_rparam);
+    dfree(c->d_rop);
+    dfree(c->d_pass);
+    dfree(c->d_res);
+    dfree(c->d_comp);
+    dfree(c->d_codes);
+    c->plan_valid = false;
+}
+
+void free_state_buffers(pp_circuit *c) {
+    free_graph(c);
+    dfree(c->coef);
+    dfree(c->pres);
+    dfree(c->d_counters);
+    dfree(c->d_result);
+    dfree(c->d_partials);
+    for (void *&p : c->sb_base) dfree(p);
+    dfree(c->sb.count);
+    dfree(c->sb.updates);
+    dfree(c->sb.hist);
+    dfree(c->sb.tile_flags);
+    c->sb = pp::SparseBuffers{};
+}
+
+int64_t dense_slots(int n) { return (int64_t)1 << (2 * n); }
+
+uint64_t g_plan_gen = 0;
+
+int tile_qubits_for(const pp_circuit *c) {
+    if (c->n <= kResidentMaxN &&
+        pp::resident_lds_bytes(c->n, c->dbytes, c->track != 0) <= (size_t)pp::max_lds_bytes())
+        return c->n;
+    int k = c->tile_opt > 0 ? c->tile_opt : default_tile_qubits(c->n);
+    k = std::min(k, c->n - 1);
+    k = std::max(k, kLowQubits + 2);
+    k = std::min(k, 7);
+    while (k > kLowQubits + 2 && pp::resident_lds_bytes(k, c->dbytes, c->track != 0) > (size_t)pp::max_lds_bytes())
+        --k;
+    return k;
+}
+
+pp_status ensure_state(pp_circuit *c) {
+    if (c->engine == PP_ENGINE_DENSE) {
+        const int64_t slots = dense_slots(c->n);
+        if (!c->coef) {
+            hipError_t e = hipMalloc(&c->coef, (size_t)slots * c->dbytes);
+            if (e != hipSuccess) {
+                c->coef = nullptr;
+                return fail(PP_ERR_NOMEM, "dense weights: " + std::to_string(slots * c->dbytes) + " bytes");
+            }
+        }
+        if (c->track && !c->pres) HIPCHK(dalloc(&c->pres, (size_t)slots));
+    } else if (!c->sb.x) {
+        int64_t cap = c->max_terms > 0 ? c->max_terms : (c->n <= 12 ? dense_slots(c->n) : ((int64_t)1 << 24));
+        if (c->n <= 12) cap = std::min<int64_t>(cap, dense_slots(c->n));
+        cap = std::max<int64_t>(cap, 1);
+        const int64_t cap2 = 2 * cap;
+        const int64_t tiles = (cap2 + 2047) / 2048;
+        c->sb.cap2 = cap2;
+        c->sb.max_tiles = tiles;
+        for (int i = 0; i < 6; ++i) {
+            const size_t bytes = (size_t)cap2 * ((i == 2 || i == 5) ? c->dbytes : 8);
+            hipError_t e = hipMalloc(&c->sb_base[i], bytes);
+            if (e != hipSuccess) {
+                c->sb_base[i] = nullptr;
+                return fail(PP_ERR_NOMEM, "sparse term buffers");
+            }
+        }
+        c->sb.x = (uint64_t *)c->sb_base[0];
+        c->sb.z = (uint64_t *)c->sb_base[1];
+        c->sb.c = c->sb_base[2];
+        c->sb.x2 = (uint64_t *)c->sb_base[3];
+        c->sb.z2 = (uint64_t *)c->sb_base[4];
+        c->sb.c2 = c->sb_base[5];
+        HIPCHK(dalloc(&c->sb.count, 4));
+        HIPCHK(dalloc(&c->sb.updates, 1));
+        HIPCHK(dalloc(&c->sb.hist, (size_t)256 * tiles));
+        HIPCHK(dalloc(&c->sb.tile_flags, (size_t)tiles));
+        HIPCHK(dalloc(&c->d_partials, 256));
+    }
+    if (!c->d_counters) HIPCHK(dalloc(&c->d_counters, 4));
+    if (!c->d_result) HIPCHK(dalloc(&c->d_result, 1));
+    return PP_OK;
+}
+
+template <class T>
+pp_status upload_vec(T **dptr, const std::vector<T> &v) {
+    dfree(*dptr);
+    HIPCHK(dalloc(dptr, v.size()));
+    if (!v.empty()) HIPCHK(hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PP_OK;
+}
+
+pp_status ensure_plan(pp_circuit *c) {
+    pp_status r = ensure_state(c);
+    if (r != PP_OK) return r;
+    const int k = c->engine == PP_ENGINE_DENSE ? tile_qubits_for(c) : 0;
+    if (c->plan_valid && c->plan_track == c->track && c->plan_k == k) return PP_OK;
+    free_plan_buffers(c);
+    if (c->track && c->engine == PP_ENGINE_DENSE && !c->pres) HIPCHK(dalloc(&c->pres, (size_t)dense_slots(c->n)));
+    if (c->engine == PP_ENGINE_SPARSE) {
+        c->splan = pp::plan_sparse(c->g);
+        if ((r = upload_vec(&c->d_codes, c->splan.codes)) != PP_OK) return r;
+    } else {
+        c->dplan = pp::plan_dense(c->g, k, kLowQubits, c->track == 0, c->track == 0);
+        const pp::DensePlan &P = c->dplan;
+        if ((r = upload_vec(&c->d_ops, P.ops)) != PP_OK) return r;
+        if ((r = upload_vec(&c->d_roff, P.roff)) != PP_OK) return r;
+        if ((r = upload_vec(&c->d_rop, P.rop)) != PP_OK) return r;
+        if ((r = upload_vec(&c->d_rparam, P.rparam)) != PP_OK) return r;
+        HIPCHK(dalloc(&c->d_maps, (size_t)9 * std::max(P.nmaps(), 1)));
+        c->h_comp = pp::ComposeDesc{c->d_roff, c->d_rop, c->d_rparam, c->d_theta, c->d_maps, P.nmaps(), 0};
+        HIPCHK(dalloc(&c->d_comp, 1));
+        HIPCHK(hipMemcpy(c->d_comp, &c->h_comp, sizeof(c->h_comp), hipMemcpyHostToDevice));
+        if (P.resident) {
+            pp::ResidentDesc &d = c->h_res;
+            d = pp::ResidentDesc{};
+            d.coef_out = c->track ? c->coef : nullptr;
+            d.pres_out = c->track ? c->pres : nullptr;
+            d.ops = c->d_ops;
+            d.maps = c->d_maps;
+            d.obs_x = c->d_ox;
+            d.obs_z = c->d_oz;
+            d.obs_c = c->d_oc;
+            d.expval_out = c->d_result;
+            d.counters = c->d_counters;
+            d.nops = (int32_t)P.ops.size();
+            d.n = c->n;
+            d.nterms = (int32_t)c->ox.size();
+            HIPCHK(dalloc(&c->d_res, 1));
+            HIPCHK(hipMemcpy(c->d_res, &d, sizeof(d), hipMemcpyHostToDevice));
+        } else {
+            c->h_pass.clear();
+            const int ntiles = (int)((int64_t)1 << (2 * (c->n - k)));
+            for (const pp::DensePass &ps : P.passes) {
+                pp::TilePassDesc d{};
+                d.coef = c->coef;
+                d.pres = c->track ? c->pres : nullptr;
+                d.ops = c->d_ops;
+                d.maps = c->d_maps;
+                d.counters = c->d_counters;
+                d.n = c->n;
+                d.k = k;
+                d.op_begin = ps.op_begin;
+                d.op_end = ps.op_end;
+                d.tile_begin = 0;
+                d.ntiles = ntiles;
+                for (int j = 0; j < 8; ++j) d.qubit[j] = ps.qubit[j];
+                c->h_pass.push_back(d);
+            }
+            if ((r = upload_vec(&c->d_pass, c->h_pass)) != PP_OK) return r;
+        }
+    }
+    c->plan_valid = true;
+    c->plan_track = c->track;
+    c->plan_k = k;
+    c->plan_gen = ++g_plan_gen;
+    return PP_OK;
+}
+
+pp_status check_ready(pp_circuit *c) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    if (!c->have_gates) return fail(PP_ERR_STATE, "gates not loaded");
+    if (!c->have_theta) return fail(PP_ERR_STATE, "theta not set");
+    if (!c->have_obs) return fail(PP_ERR_STATE, "observable not set");
+    return PP_OK;
+}
+
+void fill_plan_stats(pp_circuit *c) {
+    pp_stats &s = c->st;
+    s.gates = c->g.m;
+    s.engine = c->engine;
+    if (c->engine == PP_ENGINE_DENSE) {
+        const pp::DensePlan &P = c->dplan;
+        s.ops = (int64_t)P.ops.size();
+        s.passes = (int64_t)P.passes.size();
+        s.tile_qubits = P.k;
+        const int64_t slots = dense_slots(c->n);
+        const int64_t per = 2 * slots * (c->dbytes + (c->track ? 1 : 0));
+        if (P.resident) {
+            s.launches = 1 + (P.nmaps() > 0 ? 1 : 0);
+            s.bytes_per_eval = 0;
+        } else {
+            s.launches = (int64_t)P.passes.size() + 3 + (P.nmaps() > 0 ? 1 : 0) + (c->track ? 1 : 0);
+            s.bytes_per_eval = per * (int64_t)P.passes.size();
+        }
+    } else {
+        const pp::SparsePlan &P = c->splan;
+        s.ops = (int64_t)P.passes.size();
+        s.passes = (int64_t)P.passes.size();
+        s.tile_qubits = 0;
+        int rot = 0;
+        for (auto &p : P.passes) rot += p.rot_op >= 3;
+        const int dig = (2 * c->n + 7) / 8;
+        s.launches = 2 + 3 * (int64_t)P.passes.size() + (int64_t)(rot + 1) * (3 * dig + 3) + 2;
+        s.bytes_per_eval = 0;  // known after the run (48 or 40 bytes per update)
+    }
+}
+
+pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
+    const pp::DensePlan &P = c->dplan;
+    if (c->track) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, c->d_counters, 4);
+    if (P.nmaps() > 0) {
+        ProfScope ps(PC_COMPOSE, s);
+        HIPCHK(pp::launch_compose(c->d_comp, 1, s));
+    }
+    if (P.resident) {
+        {
+            ProfScope ps(PC_RES, s);
+            HIPCHK(pp::launch_resident(c->d_res, 1, c->n, c->dbytes, c->track != 0, s));
+        }
+        hipLaunchKernelGGL(copy_f64_kernel, dim3(1), dim3(64), 0, s, c->d_result, out, 1);
+        HIPCHK(hipGetLastError());
+        return PP_OK;
+    }
+    {
+        ProfScope ps(PC_INIT, s);
+        HIPCHK(pp::launch_dense_init(c->coef, c->track ? c->pres : nullptr, c->n, c->dbytes, c->d_ox, c->d_oz,
+                                     c->d_oc, (int)c->ox.size(), s));
+    }
+    const int ntiles = (int)((int64_t)1 << (2 * (c->n - P.k)));
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        ProfScope ps(PC_TILE, s);
+        HIPCHK(pp::launch_tile_pass(c->d_pass + p, 1, ntiles, P.k, c->dbytes, c->track != 0, s));
+    }
+    {
+        ProfScope ps(PC_READOUT, s);
+        HIPCHK(pp::launch_dense_readout(c->coef, c->n, c->dbytes, out, s));
+    }
+    if (c->track) HIPCHK(pp::launch_dense_count(c->pres, c->n, c->d_counters + 1, s));
+    return PP_OK;
+}
+
+pp_status enqueue_sparse(pp_circuit *c, hipStream_t s, double *out) {
+    const pp::SparsePlan &P = c->splan;
+    if ((int64_t)c->ox.size() > c->sb.cap2) return fail(PP_ERR_CAPACITY, "observable larger than the term capacity");
+    HIPCHK(pp::launch_sparse_init(c->sb, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+    bool merged_last = true;
+    for (const pp::SparsePassDesc &p : P.passes) {
+        {
+            ProfScope ps(PC_SPASS, s);
+            HIPCHK(pp::launch_sparse_pass(c->sb, c->dbytes, c->d_codes, p, c->d_theta, s));
+        }
+        merged_last = false;
+        if (p.rot_op >= 3) {
+            ProfScope ps(PC_SMERGE, s);
+            HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s));
+            merged_last = true;
+        }
+    }
+    if (!merged_last) {
+        ProfScope ps(PC_SMERGE, s);
+        HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s));
+    }
+    {
+        ProfScope ps(PC_READOUT, s);
+        HIPCHK(pp::launch_sparse_readout(c->sb, c->dbytes, c->d_partials, out, s));
+    }
+    return PP_OK;
+}
+
+}  // namespace
+
+// ===================================================================== API
+extern "C" {
+
+const char *pp_version(void) { return "pauliprop 0.1 (gfx950)"; }
+
+const char *pp_last_error(void) { return g_err.c_str(); }
+
+pp_status pp_circuit_create(int32_t n_qubits, pp_dtype dtype, pp_engine engine, pp_circuit **out) {
+    if (!out) return fail(PP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 64) return fail(PP_ERR_INVALID, "n_qubits must be in [1, 64]");
+    if (dtype != PP_F64 && dtype != PP_F32) return fail(PP_ERR_INVALID, "unknown dtype");
+    if (engine != PP_ENGINE_AUTO && engine != PP_ENGINE_DENSE && engine != PP_ENGINE_SPARSE)
+        return fail(PP_ERR_INVALID, "unknown engine");
+    int resolved = engine;
+    if (engine == PP_ENGINE_AUTO) resolved = n_qubits <= kAutoDenseMaxN ? PP_ENGINE_DENSE : PP_ENGINE_SPARSE;
+    if (resolved == PP_ENGINE_DENSE && n_qubits > kDenseMaxN)
+        return fail(PP_ERR_CAPACITY, "DENSE engine supports n <= 16");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PP_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    pp_circuit *c = new (std::nothrow) pp_circuit();
+    if (!c) return fail(PP_ERR_NOMEM, "host allocation");
+    c->n = n_qubits;
+    c->dtype = dtype;
+    c->dbytes = dtype == PP_F64 ? 8 : 4;
+    c->req = engine;
+    c->engine = resolved;
+    c->g.n = n_qubits;
+    *out = c;
+    return PP_OK;
+}
+
+void pp_circuit_destroy(pp_circuit *c) {
+    if (!c) return;
+    if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+    (void)hipDeviceSynchronize();
+    free_plan_buffers(c);
+    free_state_buffers(c);
+    dfree(c->d_theta);
+    dfree(c->d_ox);
+    dfree(c->d_oz);
+    dfree(c->d_oc);
+    c->staging.release();
+    delete c;
+}
+
+pp_status pp_circuit_load_gates(pp_circuit *c, int64_t m, const uint8_t *op, const int32_t *q0, const int32_t *q1,
+                                const int32_t *param, int32_t n_params) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    if (m < 0 || n_params < 0) return fail(PP_ERR_INVALID, "negative size");
+    if (m > 0 && (!op || !q0 || !q1 || !param)) return fail(PP_ERR_INVALID, "null gate array");
+    for (int64_t g = 0; g < m; ++g) {
+        if (op[g] > PP_RZ) return fail(PP_ERR_INVALID, "unknown op at gate " + std::to_string(g));
+        if (q0[g] < 0 || q0[g] >= c->n) return fail(PP_ERR_INVALID, "qubit out of range at gate " + std::to_string(g));
+        if (op[g] == PP_CX && (q1[g] < 0 || q1[g] >= c->n || q1[g] == q0[g]))
+            return fail(PP_ERR_INVALID, "bad CX target at gate " + std::to_string(g));
+        if (op[g] >= PP_RX && (param[g] < 0 || param[g] >= n_params))
+            return fail(PP_ERR_INVALID, "parameter index out of range at gate " + std::to_string(g));
+    }
+    if (c->engine == PP_ENGINE_DENSE && m > 0 && c->n > 32)
+        return fail(PP_ERR_INVALID, "DENSE engine needs n <= 32");
+    if ((int64_t)n_params > c->theta_cap) {
+        double *nt = nullptr;
+        HIPCHK(dalloc(&nt, (size_t)n_params));
+        dfree(c->d_theta);
+        c->d_theta = nt;
+        c->theta_cap = n_params;
+        c->have_theta = false;
+    }
+    if (n_params != c->g.n_params) c->have_theta = n_params == 0;
+    c->g.m = m;
+    c->g.op.assign(op, op + m);
+    c->g.q0.assign(q0, q0 + m);
+    c->g.q1.resize(m);
+    c->g.param.resize(m);
+    for (int64_t g = 0; g < m; ++g) {
+        c->g.q1[g] = op[g] == PP_CX ? q1[g] : -1;
+        c->g.param[g] = op[g] >= PP_RX ? param[g] : -1;
+    }
+    c->g.n_params = n_params;
+    if (n_params == 0) c->have_theta = true;
+    c->have_gates = true;
+    free_plan_buffers(c);
+    c->evaluated = false;
+    return PP_OK;
+}
+
+pp_status pp_circuit_set_theta(pp_circuit *c, const double *theta, int32_t on_device, void *stream) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    if (!c->have_gates) return fail(PP_ERR_STATE, "load gates first");
+    const int np = c->g.n_params;
+    if (np == 0) {
+        c->have_theta = true;
+        return PP_OK;
+    }
+    if (!theta) return fail(PP_ERR_INVALID, "theta is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (on_device) {
+        HIPCHK(hipMemcpyAsync(c->d_theta, theta, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    } else {
+        pp_status r = c->staging.upload(c->d_theta, theta, sizeof(double) * np, s);
+        if (r != PP_OK) return r;
+    }
+    c->have_theta = true;
+    return PP_OK;
+}
+
+pp_status pp_circuit_set_observable(pp_circuit *c, int64_t n_terms, const uint64_t *x, const uint64_t *z,
+                                    const double *coeff) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    if (n_terms < 1 || n_terms > (1 << 30)) return fail(PP_ERR_INVALID, "n_terms must be in [1, 2^30]");
+    if (!x || !z || !coeff) return fail(PP_ERR_INVALID, "null observable array");
+    const uint64_t mask = c->n >= 64 ? ~0ull : ((1ull << c->n) - 1ull);
+    for (int64_t k = 0; k < n_terms; ++k)
+        if ((x[k] & ~mask) || (z[k] & ~mask)) return fail(PP_ERR_INVALID, "observable bit at or above n");
+    uint64_t *dx = nullptr, *dz = nullptr;
+    double *dc = nullptr;
+    HIPCHK(dalloc(&dx, (size_t)n_terms));
+    HIPCHK(dalloc(&dz, (size_t)n_terms));
+    HIPCHK(dalloc(&dc, (size_t)n_terms));
+    HIPCHK(hipMemcpy(dx, x, sizeof(uint64_t) * n_terms, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dz, z, sizeof(uint64_t) * n_terms, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dc, coeff, sizeof(double) * n_terms, hipMemcpyHostToDevice));
+    dfree(c->d_ox);
+    dfree(c->d_oz);
+    dfree(c->d_oc);
+    c->d_ox = dx;
+    c->d_oz = dz;
+    c->d_oc = dc;
+    c->ox.assign(x, x + n_terms);
+    c->oz.assign(z, z + n_terms);
+    c->oc.assign(coeff, coeff + n_terms);
+    c->have_obs = true;
+    free_plan_buffers(c);  // descriptors hold the observable pointers
+    return PP_OK;
+}
+
+pp_status pp_circuit_set_option(pp_circuit *c, pp_option key, int64_t value) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    switch (key) {
+    case PP_OPT_TRACK_TERMS:
+        c->track = value ? 1 : 0;
+        free_graph(c);
+        return PP_OK;
+    case PP_OPT_TILE_QUBITS:
+        if (value != 0 && (value < 4 || value > 7)) return fail(PP_ERR_INVALID, "tile qubits must be 0 or 4..7");
+        c->tile_opt = (int)value;
+        free_graph(c);
+        return PP_OK;
+    case PP_OPT_MAX_TERMS:
+        if (value < 0) return fail(PP_ERR_INVALID, "max terms must be >= 0");
+        c->max_terms = value;
+        free_state_buffers(c);
+        free_plan_buffers(c);
+        return PP_OK;
+    case PP_OPT_USE_GRAPH:
+        c->use_graph = value ? 1 : 0;
+        free_graph(c);
+        return PP_OK;
+    case PP_OPT_BLOCK:
+        if (value != 0 && (value < 64 || value > 1024 || (value & 63))) return fail(PP_ERR_INVALID, "bad block size");
+        c->block = (int)value;
+        return PP_OK;
+    }
+    return fail(PP_ERR_INVALID, "unknown option");
+}
+
+pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval) {
+    pp_status r = check_ready(c);
+    if (r != PP_OK) return r;
+    if (!d_expval) return fail(PP_ERR_INVALID, "d_expval is NULL");
+    if ((r = ensure_plan(c)) != PP_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    fill_plan_stats(c);
+    if (c->engine == PP_ENGINE_SPARSE) {
+        r = enqueue_sparse(c, s, d_expval);
+    } else if (c->use_graph && !c->dplan.resident) {
+        if (!c->gexec) {
+            hipStream_t cs;
+            HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                g_prof.capturing++;
+                r = enqueue_dense_body(c, cs, c->d_result);
+                g_prof.capturing--;
+                hipGraph_t gr = nullptr;
+                hipError_t e2 = hipStreamEndCapture(cs, &gr);
+                if (r == PP_OK && e2 == hipSuccess) {
+                    c->graph = gr;
+                    e2 = hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0);
+                }
+                if (e2 != hipSuccess && r == PP_OK) r = fail(PP_ERR_DEVICE, "graph capture failed");
+            } else {
+                r = fail(PP_ERR_DEVICE, "hipStreamBeginCapture failed");
+            }
+            (void)hipStreamDestroy(cs);
+            if (r != PP_OK) {
+                free_graph(c);
+                return r;
+            }
+        }
+        HIPCHK(hipGraphLaunch(c->gexec, s));
+        hipLaunchKernelGGL(copy_f64_kernel, dim3(1), dim3(64), 0, s, c->d_result, d_expval, 1);
+        HIPCHK(hipGetLastError());
+    } else {
+        r = enqueue_dense_body(c, s, d_expval);
+    }
+    if (r != PP_OK) return r;
+    c->evaluated = true;
+    c->last_track = c->track;
+    c->last_stream = s;
+    return PP_OK;
+}
+
+pp_status pp_get_stats(pp_circuit *c, pp_stats *out) {
+    if (!c || !out) return fail(PP_ERR_INVALID, "null argument");
+    if (c->evaluated) {
+        HIPCHK(hipStreamSynchronize(c->last_stream));
+        if (c->engine == PP_ENGINE_SPARSE) {
+            long long cnt[2] = {0, 0};
+            unsigned long long upd = 0;
+            HIPCHK(hipMemcpy(cnt, c->sb.count, sizeof(cnt), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(&upd, c->sb.updates, sizeof(upd), hipMemcpyDeviceToHost));
+            c->st.term_updates = (int64_t)upd;
+            c->st.final_terms = cnt[0];
+            c->st.overflow = (int32_t)cnt[1];
+            c->st.bytes_per_eval = (int64_t)upd * (16 + 2 * (int64_t)c->dbytes) ;
+        } else if (c->last_track) {
+            unsigned long long cnt[2] = {0, 0};
+            HIPCHK(hipMemcpy(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+            c->st.term_updates = (int64_t)cnt[0];
+            c->st.final_terms = (int64_t)cnt[1];
+        }
+    }
+    *out = c->st;
+    return PP_OK;
+}
+
+pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *x, uint64_t *z, double *coeff,
+                       int64_t *n_out) {
+    if (!c || !n_out) return fail(PP_ERR_INVALID, "null argument");
+    if (capacity > 0 && (!x || !z || !coeff)) return fail(PP_ERR_INVALID, "null output array");
+    if (!c->evaluated) return fail(PP_ERR_STATE, "no evaluation yet");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->engine == PP_ENGINE_DENSE && !c->last_track)
+        return fail(PP_ERR_STATE, "DENSE needs PP_OPT_TRACK_TERMS = 1 for the evaluation");
+    const uint64_t *sx = nullptr, *sz = nullptr;
+    const void *sc = nullptr;
+    int cbytes = c->dbytes;
+    pp::SparseBuffers tmp{};
+    void *tmp_base[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    long long count = 0;
+    pp_status r = PP_OK;
+    if (c->engine == PP_ENGINE_SPARSE) {
+        HIPCHK(hipStreamSynchronize(s));
+        long long cnt[2];
+        HIPCHK(hipMemcpy(cnt, c->sb.count, sizeof(cnt), hipMemcpyDeviceToHost));
+        if (cnt[1]) return fail(PP_ERR_CAPACITY, "term capacity was exceeded during the evaluation");
+        count = cnt[0];
+        sx = c->sb.x;
+        sz = c->sb.z;
+        sc = c->sb.c;
+    } else {
+        // compact present slots, then sort them into canonical order
+        const int64_t slots = dense_slots(c->n);
+        const int64_t tiles = (slots + 2047) / 2048;
+        tmp.cap2 = slots;
+        tmp.max_tiles = tiles;
+        bool ok = true;
+        for (int i = 0; i < 6 && ok; ++i) ok = hipMalloc(&tmp_base[i], (size_t)slots * 8) == hipSuccess;
+        ok = ok && hipMalloc((void **)&tmp.count, 4 * sizeof(long long)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&tmp.updates, sizeof(unsigned long long)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&tmp.hist, (size_t)256 * tiles * sizeof(unsigned)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&tmp.tile_flags, (size_t)std::max<int64_t>(tiles, slots / 4096 + 1) * sizeof(int)) ==
+                       hipSuccess;
+        unsigned long long *total = c->d_counters + 2;
+        if (ok) {
+            tmp.x = (uint64_t *)tmp_base[0];
+            tmp.z = (uint64_t *)tmp_base[1];
+            tmp.c = tmp_base[2];
+            tmp.x2 = (uint64_t *)tmp_base[3];
+            tmp.z2 = (uint64_t *)tmp_base[4];
+            tmp.c2 = tmp_base[5];
+            hipError_t e = pp::launch_dense_compact(c->coef, c->pres, c->n, c->dbytes, tmp.x, tmp.z, (double *)tmp.c,
+                                                    total, tmp.tile_flags, nullptr, nullptr, s);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(compact_to_sparse_count_kernel, dim3(1), dim3(64), 0, s, total, tmp.count);
+                e = pp::launch_sparse_merge(tmp, c->n, 8, s);
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) e = hipMemcpy(&count, tmp.count, sizeof(count), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) r = fail(PP_ERR_DEVICE, std::string("terms dump: ") + hipGetErrorString(e));
+        } else {
+            r = fail(PP_ERR_NOMEM, "terms dump scratch");
+        }
+        sx = tmp.x;
+        sz = tmp.z;
+        sc = tmp.c;
+        cbytes = 8;
+    }
+    if (r == PP_OK) {
+        *n_out = count;
+        const int64_t k = std::min<int64_t>(count, capacity);
+        if (k > 0) {
+            hipError_t e = hipMemcpy(x, sx, sizeof(uint64_t) * k, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(z, sz, sizeof(uint64_t) * k, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) {
+                if (cbytes == 8) {
+                    e = hipMemcpy(coeff, sc, sizeof(double) * k, hipMemcpyDeviceToHost);
+                } else {
+                    std::vector<float> f((size_t)k);
+                    e = hipMemcpy(f.data(), sc, sizeof(float) * k, hipMemcpyDeviceToHost);
+                    for (int64_t i = 0; i < k; ++i) coeff[i] = (double)f[i];
+                }
+            }
+            if (e != hipSuccess) r = fail(PP_ERR_DEVICE, std::string("terms copy: ") + hipGetErrorString(e));
+        }
+        if (r == PP_OK && count > capacity) r = fail(PP_ERR_CAPACITY, "capacity smaller than the term count");
+    }
+    for (void *&p : tmp_base) dfree(p);
+    dfree(tmp.count);
+    dfree(tmp.updates);
+    dfree(tmp.hist);
+    dfree(tmp.tile_flags);
+    return r;
+}
+
+}  // extern "C"
+
+// ================================================================ batching
+namespace {
+
+// Device descriptors of the last batch, reused while the same circuits (with
+// unchanged schedules) are evaluated into the same output array.
+struct BatchCache {
+    std::vector<const pp_circuit *> key;
+    std::vector<uint64_t> gens;
+    double *out = nullptr;
+    void *dbuf = nullptr;
+    size_t dcap = 0;
+    Staging staging;
+    hipEvent_t done = nullptr;
+    struct Launch { int kind; int group_n; int off; int nd; int nblocks; };
+    std::vector<Launch> launches;  // kind 0 compose, 1 resident, 2 tile pass
+    std::vector<int> tiled;        // indices of tiled circuits
+    std::vector<int> single;       // indices evaluated one by one
+};
+BatchCache g_batch;
+
+}  // namespace
+
+extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, void *stream, double *d_expvals) {
+    if (count < 0 || (count > 0 && (!cs || !d_expvals))) return fail(PP_ERR_INVALID, "bad batch arguments");
+    if (count == 0) return PP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    pp_status r;
+    int dbytes = -1;
+    for (int64_t i = 0; i < count; ++i) {
+        if ((r = check_ready(cs[i])) != PP_OK) return r;
+        if ((r = ensure_plan(cs[i])) != PP_OK) return r;
+        fill_plan_stats(cs[i]);
+        if (cs[i]->engine == PP_ENGINE_DENSE && !cs[i]->track) {
+            if (dbytes >= 0 && dbytes != cs[i]->dbytes) return fail(PP_ERR_INVALID, "mixed dtypes in one batch");
+            dbytes = cs[i]->dbytes;
+        }
+    }
+    BatchCache &B = g_batch;
+    bool hit = B.out == d_expvals && B.key.size() == (size_t)count;
+    for (int64_t i = 0; hit && i < count; ++i) hit = B.key[i] == cs[i] && B.gens[i] == cs[i]->plan_gen;
+    if (!hit) {
+        if (B.done) HIPCHK(hipEventSynchronize(B.done));
+        B.key.assign(cs, cs + count);
+        B.gens.resize(count);
+        for (int64_t i = 0; i < count; ++i) B.gens[i] = cs[i]->plan_gen;
+        B.out = d_expvals;
+        B.launches.clear();
+        B.tiled.clear();
+        B.single.clear();
+        std::vector<unsigned char> blob;
+        auto append = [&](const void *p, size_t bytes) {
+            const size_t off = blob.size();
+            blob.resize(off + ((bytes + 15) & ~size_t(15)));
+            std::memcpy(blob.data() + off, p, bytes);
+            return (int)off;
+        };
+        std::vector<pp::ComposeDesc> comp;
+        std::vector<std::vector<int>> res_by_n(kResidentMaxN + 1);
+        for (int64_t i = 0; i < count; ++i) {
+            pp_circuit *c = cs[i];
+            if (c->engine != PP_ENGINE_DENSE || c->track) {
+                B.single.push_back((int)i);
+                continue;
+            }
+            if (c->dplan.nmaps() > 0) comp.push_back(c->h_comp);
+            if (c->dplan.resident) res_by_n[c->n].push_back((int)i);
+            else B.tiled.push_back((int)i);
+        }
+        if (!comp.empty())
+            B.launches.push_back({0, 0, append(comp.data(), comp.size() * sizeof(comp[0])), (int)comp.size(), 0});
+        // resident groups, largest size class first, longest circuits first
+        for (int n = kResidentMaxN; n >= 1; --n) {
+            auto &v = res_by_n[n];
+            if (v.empty()) continue;
+            std::stable_sort(v.begin(), v.end(),
+                             [&](int a, int b) { return cs[a]->dplan.ops.size() > cs[b]->dplan.ops.size(); });
+            std::vector<pp::ResidentDesc> rd;
+            for (int i : v) {
+                pp::ResidentDesc d = cs[i]->h_res;
+                d.expval_out = d_expvals + i;
+                rd.push_back(d);
+            }
+            B.launches.push_back({1, n, append(rd.data(), rd.size() * sizeof(rd[0])), (int)rd.size(), 0});
+        }
+        // tiled circuits: pass l of every circuit that has one, per tile size
+        for (int k = 4; k <= 7; ++k) {
+            std::vector<int> grp;
+            size_t maxp = 0;
+            for (int i : B.tiled)
+                if (cs[i]->dplan.k == k) {
+                    grp.push_back(i);
+                    maxp = std::max(maxp, cs[i]->dplan.passes.size());
+                }
+            for (size_t l = 0; l < maxp; ++l) {
+                std::vector<pp::TilePassDesc> td;
+                int run = 0;
+                for (int i : grp) {
+                    if (l >= cs[i]->h_pass.size()) continue;
+                    pp::TilePassDesc d = cs[i]->h_pass[l];
+                    d.tile_begin = run;
+                    run += d.ntiles;
+                    td.push_back(d);
+                }
+                B.launches.push_back({2, k, append(td.data(), td.size() * sizeof(td[0])), (int)td.size(), run});
+            }
+        }
+        if (blob.size() > B.dcap) {
+            if (B.dbuf) HIPCHK(hipStreamSynchronize(s));
+            dfree(B.dbuf);
+            HIPCHK(hipMalloc(&B.dbuf, blob.size()));
+            B.dcap = blob.size();
+        }
+        if (!blob.empty()) {
+            r = B.staging.upload(B.dbuf, blob.data(), blob.size(), s);
+            if (r != PP_OK) return r;
+        }
+    }
+    unsigned char *base = (unsigned char *)B.dbuf;
+    // tiled circuits start from their observables
+    for (int i : B.tiled) {
+        pp_circuit *c = cs[i];
+        ProfScope ps(PC_INIT, s);
+        HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+    }
+    for (const auto &L : B.launches) {
+        ProfScope ps(L.kind == 0 ? PC_COMPOSE : L.kind == 1 ? PC_RES : PC_TILE, s);
+        if (L.kind == 0) {
+            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, s));
+        } else if (L.kind == 1) {
+            HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, s));
+        } else {
+            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.nd, L.nblocks, L.group_n, dbytes,
+                                        false, s));
+        }
+    }
+    for (int i : B.tiled) {
+        pp_circuit *c = cs[i];
+        ProfScope ps(PC_READOUT, s);
+        HIPCHK(pp::launch_dense_readout(c->coef, c->n, c->dbytes, d_expvals + i, s));
+    }
+    for (int i : B.single)
+        if ((r = pp_evaluate(cs[i], stream, d_expvals + i)) != PP_OK) return r;
+    if (!B.done) HIPCHK(hipEventCreateWithFlags(&B.done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(B.done, s));
+    for (int64_t i = 0; i < count; ++i) {
+        cs[i]->evaluated = true;
+        cs[i]->last_track = cs[i]->track;
+        cs[i]->last_stream = s;
+    }
+    return PP_OK;
+}
+
+extern "C" pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_every_gates, double *d_expval,
+                                 double *d_grad) {
+    (void)c; (void)stream; (void)checkpoint_every_gates; (void)d_expval; (void)d_grad;
+    return fail(PP_ERR_STATE, "gradient: not available in this build");
+}
+
+extern "C" pp_status pp_profile_enable(int32_t on) {
+    g_prof.on = on != 0;
+    return PP_OK;
+}
+
+extern "C" pp_status pp_profile_read(pp_kernel_time *out, int32_t max, int32_t *n_out) {
+    if (!n_out || (max > 0 && !out)) return fail(PP_ERR_INVALID, "null argument");
+    double ms[PC_N] = {0};
+    int64_t cnt[PC_N] = {0};
+    for (const auto &r : g_prof.recs) {
+        HIPCHK(hipEventSynchronize(g_prof.pool[r.second + 1]));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, g_prof.pool[r.second], g_prof.pool[r.second + 1]));
+        ms[r.first] += t;
+        cnt[r.first]++;
+    }
+    g_prof.recs.clear();
+    g_prof.used = 0;
+    int k = 0;
+    for (int c = 0; c < PC_N; ++c) {
+        if (!cnt[c]) continue;
+        if (k < max) {
+            std::memset(out[k].name, 0, sizeof(out[k].name));
+            std::strncpy(out[k].name, kProfNames[c], sizeof(out[k].name) - 1);
+            out[k].launches = cnt[c];
+            out[k].total_ms = ms[c];
+        }
+        ++k;
+    }
+    *n_out = std::min(k, max);
+    return PP_OK;
+}

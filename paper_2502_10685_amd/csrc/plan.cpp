@@ -1,0 +1,292 @@
+// Host planner of libpauliprop.
+//
+// The observable is propagated in the Heisenberg picture, so gates are taken
+// g_m first.  Two schedules are built from the same list:
+//
+// Dense: the paper divides a circuit into operators of non-CX gates U_k and
+// CX gates V_k and groups each U_k by wire, so that all single-qubit gates of
+// one wire act as one composed map (Sec. III-A, Sec. III-C, eq. (5)).  Here a
+// wire's run of single-qubit gates between two CX gates touching that wire
+// becomes one U1 op, whatever other wires do in between (gates on disjoint
+// qubits commute).  For n too large for one workgroup's LDS the ops are
+// packed into passes over k-qubit tiles: a greedy list scheduler takes every
+// gate whose predecessors on its wires are done and whose qubits lie in the
+// pass's qubit set, and grows the set (up to k qubits) with the earliest
+// ready gate when nothing else fits.
+//
+// Sparse: one pass per rotation, carrying the Clifford gates that precede it
+// (in Heisenberg order), so every Clifford is fused into a rotation's pass.
+#include "plan.h"
+
+#include <algorithm>
+
+namespace pp {
+
+// Heisenberg maps on the (X, Y, Z) weights, rows = output letter.
+unsigned gate_smask(int op) {
+    auto bit = [](int r, int c) { return 1u << (3 * r + c); };
+    switch (op) {
+    case 0: return bit(0, 2) | bit(1, 1) | bit(2, 0);                                  // H
+    case 1: return bit(0, 1) | bit(1, 0) | bit(2, 2);                                  // S
+    case 3: return bit(0, 0) | bit(1, 1) | bit(1, 2) | bit(2, 1) | bit(2, 2);          // RX
+    case 4: return bit(0, 0) | bit(0, 2) | bit(1, 1) | bit(2, 0) | bit(2, 2);          // RY
+    default: return bit(0, 0) | bit(0, 1) | bit(1, 0) | bit(1, 1) | bit(2, 2);         // RZ
+    }
+}
+
+// boolean product after * before
+unsigned smask_compose(unsigned after, unsigned before) {
+    unsigned out = 0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            bool v = false;
+            for (int t = 0; t < 3; ++t)
+                v = v || (((after >> (3 * r + t)) & 1u) && ((before >> (3 * t + c)) & 1u));
+            if (v) out |= 1u << (3 * r + c);
+        }
+    return out;
+}
+
+DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder) {
+    DensePlan P;
+    const int n = g.n;
+    P.roff.push_back(0);
+    P.k = k;
+    P.resident = (k >= n);
+    const int64_t m = g.m;
+    // Heisenberg position h <-> gate index m-1-h
+    auto gate_of = [&](int64_t h) { return m - 1 - h; };
+
+    if (P.resident) {
+        DensePass pass;
+        pass.k = n;
+        for (int j = 0; j < n; ++j) pass.qubit[j] = (uint8_t)j;
+        // Composition needs each map's recipe to be contiguous; gates on
+        // other wires in between would interleave recipes.  Collect, per op,
+        // its gates first, then emit recipes in op order.
+        struct Pending { int digit; std::vector<std::pair<uint8_t, int32_t>> gates; };
+        std::vector<Pending> pend;
+        std::vector<int> open(n, -1);
+        std::vector<DOp> ops;
+        for (int64_t h = 0; h < m; ++h) {
+            const int64_t gi = gate_of(h);
+            const uint8_t op = g.op[gi];
+            if (op == 2) {
+                DOp d{};
+                d.kind = DOP_CX;
+                d.a = (uint8_t)g.q0[gi];
+                d.b = (uint8_t)g.q1[gi];
+                d.ngates = 1;
+                open[g.q0[gi]] = -1;
+                open[g.q1[gi]] = -1;
+                ops.push_back(d);
+                continue;
+            }
+            const int q = g.q0[gi];
+            const bool rot = op >= 3;
+            if (compose && open[q] >= 0 && ops[open[q]].ngates < 255) {
+                DOp &d = ops[open[q]];
+                d.ngates++;
+                d.smask = (uint16_t)smask_compose(gate_smask(op), d.smask);
+                if (rot) d.perm = 0;
+                pend[d.map].gates.push_back({op, rot ? g.param[gi] : -1});
+            } else {
+                DOp d{};
+                d.kind = DOP_U1;
+                d.a = (uint8_t)q;
+                d.ngates = 1;
+                d.smask = (uint16_t)gate_smask(op);
+                d.perm = rot ? 0 : 1;
+                d.map = (uint32_t)pend.size();
+                pend.push_back({q, {{op, rot ? g.param[gi] : -1}}});
+                open[q] = (int)ops.size();
+                ops.push_back(d);
+            }
+        }
+        for (auto &pd : pend) {
+            for (auto &e : pd.gates) {
+                P.rop.push_back(e.first);
+                P.rparam.push_back(e.second);
+            }
+            P.roff.push_back((int32_t)P.rop.size());
+        }
+        P.ops = std::move(ops);
+        pass.op_begin = 0;
+        pass.op_end = (int)P.ops.size();
+        pass.ngates = m;
+        P.passes.push_back(pass);
+        return P;
+    }
+
+    // ---- tiled passes
+    std::vector<std::vector<int64_t>> wq(n);
+    for (int64_t h = 0; h < m; ++h) {
+        const int64_t gi = gate_of(h);
+        wq[g.q0[gi]].push_back(h);
+        if (g.op[gi] == 2) wq[g.q1[gi]].push_back(h);
+    }
+    std::vector<size_t> head(n, 0);
+    auto wires = [&](int64_t h) -> uint32_t {
+        const int64_t gi = gate_of(h);
+        uint32_t w = 1u << g.q0[gi];
+        if (g.op[gi] == 2) w |= 1u << g.q1[gi];
+        return w;
+    };
+    auto ready = [&](int64_t h) {
+        uint32_t w = wires(h);
+        for (int q = 0; q < n; ++q)
+            if ((w >> q) & 1u)
+                if (head[q] >= wq[q].size() || wq[q][head[q]] != h) return false;
+        return true;
+    };
+    const uint32_t lowmask = low >= 32 ? 0xffffffffu : ((1u << std::min(low, n)) - 1u);
+    int64_t remaining = m;
+    while (remaining > 0) {
+        uint32_t S = lowmask;
+        std::vector<int64_t> sched;
+        if (!reorder) {
+            // keep the Heisenberg gate order: a pass is a maximal run of
+            // consecutive gates whose qubits fit in k
+            int64_t h = m - remaining;
+            while (h < m && __builtin_popcount(S | wires(h)) <= k) {
+                S |= wires(h);
+                sched.push_back(h++);
+                --remaining;
+            }
+        }
+        for (; reorder;) {
+            bool progress = true;
+            while (progress) {
+                progress = false;
+                for (int q = 0; q < n; ++q) {
+                    if (!((S >> q) & 1u)) continue;
+                    while (head[q] < wq[q].size()) {
+                        const int64_t h = wq[q][head[q]];
+                        const uint32_t w = wires(h);
+                        if ((w & ~S) || !ready(h)) break;
+                        for (int r = 0; r < n; ++r)
+                            if ((w >> r) & 1u) head[r]++;
+                        sched.push_back(h);
+                        --remaining;
+                        progress = true;
+                    }
+                }
+            }
+            if (__builtin_popcount(S) >= k) break;
+            int64_t best = -1;
+            for (int q = 0; q < n; ++q) {
+                if (head[q] >= wq[q].size()) continue;
+                const int64_t h = wq[q][head[q]];
+                if (!ready(h)) continue;
+                if (__builtin_popcount(S | wires(h)) > k) continue;
+                if (best < 0 || h < best) best = h;
+            }
+            if (best < 0) break;
+            S |= wires(best);
+        }
+        if (sched.empty()) break;  // cannot happen for k >= low + 2
+        // pad the qubit set to exactly k qubits with the lowest unused ones
+        for (int q = 0; q < n && __builtin_popcount(S) < k; ++q) S |= 1u << q;
+        DensePass pass;
+        pass.k = k;
+        int local[32];
+        int j = 0;
+        for (int q = 0; q < n; ++q)
+            if ((S >> q) & 1u) {
+                pass.qubit[j] = (uint8_t)q;
+                local[q] = j++;
+            }
+        pass.op_begin = (int)P.ops.size();
+        // per-pass composition with contiguous recipes (see resident case)
+        struct Pending { std::vector<std::pair<uint8_t, int32_t>> gates; };
+        std::vector<Pending> pend;
+        std::vector<int> open(k, -1);
+        const int map_base = P.nmaps();
+        for (int64_t h : sched) {
+            const int64_t gi = gate_of(h);
+            const uint8_t op = g.op[gi];
+            if (op == 2) {
+                DOp d{};
+                d.kind = DOP_CX;
+                d.a = (uint8_t)local[g.q0[gi]];
+                d.b = (uint8_t)local[g.q1[gi]];
+                d.ngates = 1;
+                open[d.a] = -1;
+                open[d.b] = -1;
+                P.ops.push_back(d);
+                continue;
+            }
+            const int dg = local[g.q0[gi]];
+            const bool rot = op >= 3;
+            if (compose && open[dg] >= 0 && P.ops[open[dg]].ngates < 255) {
+                DOp &d = P.ops[open[dg]];
+                d.ngates++;
+                d.smask = (uint16_t)smask_compose(gate_smask(op), d.smask);
+                if (rot) d.perm = 0;
+                pend[d.map - map_base].gates.push_back({op, rot ? g.param[gi] : -1});
+            } else {
+                DOp d{};
+                d.kind = DOP_U1;
+                d.a = (uint8_t)dg;
+                d.ngates = 1;
+                d.smask = (uint16_t)gate_smask(op);
+                d.perm = rot ? 0 : 1;
+                d.map = (uint32_t)(map_base + pend.size());
+                pend.push_back({{{op, rot ? g.param[gi] : -1}}});
+                open[dg] = (int)P.ops.size();
+                P.ops.push_back(d);
+            }
+        }
+        for (auto &pd : pend) {
+            for (auto &e : pd.gates) {
+                P.rop.push_back(e.first);
+                P.rparam.push_back(e.second);
+            }
+            P.roff.push_back((int32_t)P.rop.size());
+        }
+        pass.op_end = (int)P.ops.size();
+        pass.ngates = (int64_t)sched.size();
+        P.passes.push_back(pass);
+    }
+    return P;
+}
+
+SparsePlan plan_sparse(const GateList &g) {
+    SparsePlan P;
+    const int64_t m = g.m;
+    SparsePassDesc cur{};
+    cur.g_begin = 0;
+    cur.rot_op = -1;
+    int ng = 0;
+    for (int64_t h = 0; h < m; ++h) {
+        const int64_t gi = m - 1 - h;
+        const uint8_t op = g.op[gi];
+        if (op <= 2) {
+            const uint32_t b = op == 2 ? (uint32_t)g.q1[gi] : 0u;
+            P.codes.push_back((uint32_t)op | ((uint32_t)g.q0[gi] << 8) | (b << 16));
+            ++ng;
+            continue;
+        }
+        cur.g_end = (int32_t)P.codes.size();
+        cur.rot_op = op;
+        cur.rot_q = g.q0[gi];
+        cur.rot_param = g.param[gi];
+        cur.ngates = ng + 1;
+        P.passes.push_back(cur);
+        cur = SparsePassDesc{};
+        cur.g_begin = (int32_t)P.codes.size();
+        cur.rot_op = -1;
+        ng = 0;
+    }
+    if (ng > 0) {
+        cur.g_end = (int32_t)P.codes.size();
+        cur.rot_op = -1;
+        cur.rot_q = 0;
+        cur.rot_param = 0;
+        cur.ngates = ng;
+        P.passes.push_back(cur);
+    }
+    return P;
+}
+
+}  // namespace pp

@@ -1,0 +1,59 @@
+// Host planner of libpauliprop: gate list -> device schedule.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "pp_device.h"
+
+namespace pp {
+
+struct GateList {
+    int n = 0;
+    int64_t m = 0;
+    std::vector<uint8_t> op;
+    std::vector<int32_t> q0, q1, param;
+    int32_t n_params = 0;
+};
+
+struct DensePass {
+    int k = 0;
+    uint8_t qubit[8] = {0};
+    int op_begin = 0, op_end = 0;
+    int64_t ngates = 0;
+};
+
+// Dense schedule.  ops are in Heisenberg order (g_m first); maps are built on
+// the device from the recipes (gate code and parameter per folded gate).
+struct DensePlan {
+    bool resident = false;  // whole circuit in one workgroup's LDS
+    int k = 0;              // tile qubits (n if resident)
+    std::vector<DOp> ops;
+    std::vector<int32_t> roff;  // nmaps + 1
+    std::vector<uint8_t> rop;
+    std::vector<int32_t> rparam;
+    std::vector<DensePass> passes;
+    int nmaps() const { return (int)roff.size() - 1; }
+};
+
+// Sparse schedule: runs of Clifford gates, each closed by one rotation.
+struct SparsePlan {
+    std::vector<uint32_t> codes;  // Clifford gate codes, Heisenberg order
+    std::vector<SparsePassDesc> passes;
+};
+
+// compose: fold consecutive single-qubit gates of a wire into one U1 op.
+// reorder: let gates on disjoint qubits move past each other when packing
+// passes.  Tracked runs disable both, because the term-update count
+// U = sum_g |set entering g| depends on the gate order.
+// k == n: one resident pass; k < n: passes of k-qubit tiles that always
+// contain the lowest `low` qubits.
+DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder);
+SparsePlan plan_sparse(const GateList &g);
+
+// structural 3x3 pattern of one gate's Heisenberg map (bit 3*row + col)
+unsigned gate_smask(int op);
+unsigned smask_compose(unsigned after, unsigned before);
+
+}  // namespace pp

@@ -1,0 +1,125 @@
+// Internal structures shared by the HIP kernels and the host runtime of
+// libpauliprop.  Not part of the public C ABI (include/pauliprop.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pp {
+
+// ---------------------------------------------------------------- dense ops
+// Dense layout: the weight of string P(x, z) lives at slot
+//   idx = sum_q (x_q << 2q) | (z_q << (2q + 1)),
+// i.e. qubit q owns the base-4 digit q (digit value x + 2z: I=0 X=1 Z=2 Y=3).
+// This is the paper's index space 0 ... 4^n - 1 (Sec. III-B) with a digit
+// order that makes a qubit's four letters one digit of the slot index.
+enum : uint8_t { DOP_U1 = 0, DOP_CX = 1 };
+
+// One device operation on an LDS tile.  U1: a composed single-qubit map on
+// local digit a (a real 3x3 matrix over the X, Y, Z weights, I is fixed).
+// CX: control digit a, target digit b.  16 bytes, read uniformly.
+struct DOp {
+    uint8_t kind;
+    uint8_t a, b;
+    uint8_t ngates;   // gates folded into this op (term-update counting)
+    uint16_t smask;   // U1: structural 3x3 pattern, bit (3*row + col)
+    uint16_t perm;    // U1: 1 if the map is a signed permutation
+    uint32_t map;     // U1: index into the 3x3 map array (9 doubles each)
+    uint32_t reserved;
+};
+static_assert(sizeof(DOp) == 16, "DOp must stay 16 bytes");
+
+// A whole circuit run inside one workgroup's LDS (n <= 7).
+struct ResidentDesc {
+    void *coef_out;            // final weights (4^n, slot order) or nullptr
+    uint8_t *pres_out;         // final presence bytes or nullptr
+    const DOp *ops;
+    const double *maps;
+    const uint64_t *obs_x, *obs_z;
+    const double *obs_c;
+    double *expval_out;
+    unsigned long long *counters;  // [0] term updates, [1] final strings
+    int32_t nops;
+    int32_t n;
+    int32_t nterms;
+    int32_t reserved;
+};
+
+// One pass of one circuit over its 4^(n-k) tiles of 4^k slots.
+struct TilePassDesc {
+    void *coef;                    // 4^n weights of the circuit
+    uint8_t *pres;                 // presence bytes (tracked runs) or nullptr
+    const DOp *ops;
+    const double *maps;
+    unsigned long long *counters;  // [0] term updates (tracked runs)
+    int32_t n, k;
+    int32_t op_begin, op_end;
+    int32_t tile_begin;            // first block of this desc in the launch
+    int32_t ntiles;
+    uint8_t qubit[8];              // global qubit of local digit j, ascending
+};
+
+// Per-circuit composition job: maps[i] = product of the gate matrices of
+// recipe entries [roff[i], roff[i+1]) in Heisenberg order.
+struct ComposeDesc {
+    const int32_t *roff;
+    const uint8_t *rop;
+    const int32_t *rparam;
+    const double *theta;
+    double *maps;
+    int32_t nmaps;
+    int32_t reserved;
+};
+
+// --------------------------------------------------------------- sparse ops
+// A sparse pass: a run of Clifford gates then (optionally) one rotation.
+// Clifford gate code: op | q0 << 8 | q1 << 16 (op in {H, S, CX}).
+struct SparsePassDesc {
+    int32_t g_begin, g_end;  // range in the Clifford code array
+    int32_t rot_op;          // 3..5 for RX/RY/RZ, -1 for none
+    int32_t rot_q;
+    int32_t rot_param;
+    int32_t ngates;          // Cliffords + rotation (term-update counting)
+};
+
+// ------------------------------------------------------------ launchers
+// Dense engine (dense.hip)
+hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s);
+hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int dtype_bytes, bool track,
+                           hipStream_t s);
+hipError_t launch_tile_pass(const TilePassDesc *d_descs, int ndescs, int nblocks, int k, int dtype_bytes,
+                            bool track, hipStream_t s);
+hipError_t launch_dense_init(void *coef, uint8_t *pres, int n, int dtype_bytes, const uint64_t *x,
+                             const uint64_t *z, const double *c, int nterms, hipStream_t s);
+hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double *out, hipStream_t s);
+hipError_t launch_dense_count(const uint8_t *pres, int n, unsigned long long *out, hipStream_t s);
+hipError_t launch_dense_compact(const void *coef, const uint8_t *pres, int n, int dtype_bytes, uint64_t *x,
+                                uint64_t *z, double *c, unsigned long long *count, int *tile_flags,
+                                unsigned long long *tile_vals, int *ticket, hipStream_t s);
+size_t resident_lds_bytes(int n, int dtype_bytes, bool track);
+int max_lds_bytes();
+
+// Sparse engine (sparse.hip)
+struct SparseBuffers {
+    uint64_t *x, *z;      // cap2 entries each
+    void *c;
+    uint64_t *x2, *z2;    // ping-pong for the sort
+    void *c2;
+    long long *count;     // [0] live strings, [1] overflow flag
+    unsigned long long *updates;
+    unsigned int *hist;   // radix histograms
+    int *tile_flags;      // decoupled look-back state
+    unsigned long long *tile_vals;
+    int *ticket;
+    int64_t cap2;         // capacity of each array (2x the term capacity)
+    int64_t max_tiles;
+};
+hipError_t launch_sparse_init(SparseBuffers &b, int dtype_bytes, const uint64_t *x, const uint64_t *z,
+                              const double *c, int nterms, hipStream_t s);
+hipError_t launch_sparse_pass(SparseBuffers &b, int dtype_bytes, const uint32_t *cliff_codes,
+                              const SparsePassDesc &p, const double *theta, hipStream_t s);
+hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStream_t s);
+hipError_t launch_sparse_readout(SparseBuffers &b, int dtype_bytes, double *partials, double *out,
+                                 hipStream_t s);
+
+}  // namespace pp
