@@ -45,6 +45,10 @@ def build_workload(name):
     elif name == "hea8":
         circs = [W.config4()]
         desc = "n=8, HEA 40 layers (1,280 gates, 960 params), O=TFIM (15 terms), seed 4"
+    elif name in ("rand10", "rand12"):
+        n = int(name[4:])
+        circs = [W.random_circuit(10 + n, n, 6000, W.obs_z(n, [0, 1]))]
+        desc = f"n={n}, 6,000 random gates (50% Clifford), O=Z0Z1, seed {10 + n}"
     else:
         raise SystemExit(f"unknown workload {name}")
     return circs, desc

@@ -180,6 +180,18 @@ PP_API pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uin
  * stream of that evaluation). */
 PP_API pp_status pp_get_stats(pp_circuit *c, pp_stats *out);
 
+/* Host-only planning introspection (no device needed): runs the DENSE
+ * scheduler on a gate list and reports the number of device ops and passes
+ * for tiles of k qubits (k = n: one LDS-resident pass).  compose = fold a
+ * wire's single-qubit gates into one op; reorder = let gates on disjoint
+ * qubits move past each other.  pass_ops (optional, capacity max_passes)
+ * receives the op count of each pass.  Same validation as
+ * pp_circuit_load_gates. */
+PP_API pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *op, const int32_t *q0,
+                                    const int32_t *q1, const int32_t *param, int32_t n_params, int32_t k,
+                                    int32_t compose, int32_t reorder, int64_t *n_ops, int64_t *n_passes,
+                                    int32_t *pass_ops, int64_t max_passes);
+
 /* Kernel timing for measurement: while enabled (on = 1), every kernel launch
  * of the library is bracketed by a pair of HIP events recorded on the stream
  * it is launched on.  on = 0 stops recording.  Not thread-safe; meant for

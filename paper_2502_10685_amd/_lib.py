@@ -64,6 +64,8 @@ def load():
         "pp_gradient": (st, [P, P, I32, P, P]),
         "pp_get_terms": (st, [P, P, I64, P, P, P, ctypes.POINTER(I64)]),
         "pp_get_stats": (st, [P, ctypes.POINTER(PPStats)]),
+        "pp_plan_dense_info": (st, [I32, I64, P, P, P, P, I32, I32, I32, I32, ctypes.POINTER(I64),
+                                    ctypes.POINTER(I64), P, I64]),
         "pp_profile_enable": (st, [I32]),
         "pp_profile_read": (st, [ctypes.POINTER(PPKernelTime), I32, ctypes.POINTER(I32)]),
     }
@@ -91,3 +93,23 @@ def profile_read():
     n = ctypes.c_int32(0)
     check(load().pp_profile_read(buf, 16, ctypes.byref(n)))
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}
+
+
+def plan_dense_info(n, op, q0, q1, param, n_params, k, compose=True, reorder=True, want_passes=False):
+    """Host-side schedule statistics: (ops, passes[, ops per pass])."""
+    import numpy as np
+    op = np.ascontiguousarray(op, dtype=np.uint8)
+    q0 = np.ascontiguousarray(q0, dtype=np.int32)
+    q1 = np.ascontiguousarray(q1, dtype=np.int32)
+    param = np.ascontiguousarray(param, dtype=np.int32)
+    nops, npass = ctypes.c_int64(0), ctypes.c_int64(0)
+    cap = int(op.shape[0]) + 1 if want_passes else 0
+    buf = np.zeros(max(cap, 1), dtype=np.int32)
+    P = ctypes.c_void_p
+    check(load().pp_plan_dense_info(int(n), int(op.shape[0]), op.ctypes.data_as(P), q0.ctypes.data_as(P),
+                                    q1.ctypes.data_as(P), param.ctypes.data_as(P), int(n_params), int(k),
+                                    int(compose), int(reorder), ctypes.byref(nops), ctypes.byref(npass),
+                                    buf.ctypes.data_as(P), cap))
+    if want_passes:
+        return nops.value, npass.value, buf[: npass.value].copy()
+    return nops.value, npass.value

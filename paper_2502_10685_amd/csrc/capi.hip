@@ -202,6 +202,25 @@ struct pp_circuit {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
 
+    // adjoint-gradient schedule and buffers (built on first pp_gradient)
+    struct Grad {
+        bool valid = false;
+        int64_t every = -1;
+        int k_heis = 0, k_fwd = 0;
+        pp::GradPlan plan;
+        pp::DOp *hops = nullptr, *fops = nullptr;
+        double *hmaps = nullptr, *fmaps = nullptr;
+        int32_t *hroff = nullptr, *hrparam = nullptr, *froff = nullptr, *frparam = nullptr;
+        uint8_t *hrop = nullptr, *frop = nullptr;
+        pp::ComposeDesc *comp = nullptr;  // [0] Heisenberg maps, [1] forward maps
+        pp::TilePassDesc *hpass = nullptr;
+        pp::ResidentDesc *hres = nullptr;  // one per segment (resident Heisenberg sweep)
+        pp::GradPassDesc *gpass = nullptr;
+        double *ckpt = nullptr, *rbuf = nullptr, *partials = nullptr, *rot_grad = nullptr;
+        int32_t *slot_param = nullptr;
+        int ncomp = 0;
+    } gr;
+
     Staging staging;
     pp_stats st{};
     bool evaluated = false;
@@ -218,8 +237,11 @@ void free_graph(pp_circuit *c) {
     c->graph = nullptr;
 }
 
+void free_grad(pp_circuit *c);
+
 void free_plan_buffers(pp_circuit *c) {
     free_graph(c);
+    free_grad(c);
     dfree(c->d_ops);
     dfree(c->d_maps);
     dfree(c->d_roff);
@@ -230,6 +252,16 @@ void free_plan_buffers(pp_circuit *c) {
     dfree(c->d_comp);
     dfree(c->d_codes);
     c->plan_valid = false;
+}
+
+void free_grad(pp_circuit *c) {
+    auto &G = c->gr;
+    if (!G.hops && !G.ckpt && !G.valid) return;
+    dfree(G.hops); dfree(G.fops); dfree(G.hmaps); dfree(G.fmaps);
+    dfree(G.hroff); dfree(G.hrparam); dfree(G.froff); dfree(G.frparam);
+    dfree(G.hrop); dfree(G.frop); dfree(G.comp); dfree(G.hpass); dfree(G.hres); dfree(G.gpass);
+    dfree(G.ckpt); dfree(G.rbuf); dfree(G.partials); dfree(G.rot_grad); dfree(G.slot_param);
+    G.valid = false;
 }
 
 void free_state_buffers(pp_circuit *c) {
@@ -253,13 +285,14 @@ uint64_t g_plan_gen = 0;
 
 int tile_qubits_for(const pp_circuit *c) {
     if (c->n <= kResidentMaxN &&
-        pp::resident_lds_bytes(c->n, c->dbytes, c->track != 0) <= (size_t)pp::max_lds_bytes())
+        pp::resident_lds_bytes(c->n, c->dbytes, c->track != 0) + pp::kStaticLdsReserve <= (size_t)pp::max_lds_bytes())
         return c->n;
     int k = c->tile_opt > 0 ? c->tile_opt : default_tile_qubits(c->n);
     k = std::min(k, c->n - 1);
     k = std::max(k, kLowQubits + 2);
     k = std::min(k, 7);
-    while (k > kLowQubits + 2 && pp::resident_lds_bytes(k, c->dbytes, c->track != 0) > (size_t)pp::max_lds_bytes())
+    while (k > kLowQubits + 2 &&
+           pp::resident_lds_bytes(k, c->dbytes, c->track != 0) + pp::kStaticLdsReserve > (size_t)pp::max_lds_bytes())
         --k;
     return k;
 }
@@ -370,7 +403,8 @@ pp_status ensure_plan(pp_circuit *c) {
                 d.op_end = ps.op_end;
                 d.tile_begin = 0;
                 d.ntiles = ntiles;
-                for (int j = 0; j < 8; ++j) d.qubit[j] = ps.qubit[j];
+                d.qubits = 0;
+                for (int j = 0; j < k; ++j) d.qubits |= (uint64_t)ps.qubit[j] << (8 * j);
                 c->h_pass.push_back(d);
             }
             if ((r = upload_vec(&c->d_pass, c->h_pass)) != PP_OK) return r;
@@ -443,10 +477,16 @@ pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
         HIPCHK(pp::launch_dense_init(c->coef, c->track ? c->pres : nullptr, c->n, c->dbytes, c->d_ox, c->d_oz,
                                      c->d_oc, (int)c->ox.size(), s));
     }
-    const int ntiles = (int)((int64_t)1 << (2 * (c->n - P.k)));
+    const int shift = 2 * (c->n - P.k);
     for (size_t p = 0; p < P.passes.size(); ++p) {
+        pp::TileGroups grp{};
+        grp.ngroups = 1;
+        grp.first_block[0] = 0;
+        grp.first_block[1] = 1 << shift;
+        grp.first_desc[0] = (int32_t)p;
+        grp.shift[0] = shift;
         ProfScope ps(PC_TILE, s);
-        HIPCHK(pp::launch_tile_pass(c->d_pass + p, 1, ntiles, P.k, c->dbytes, c->track != 0, s));
+        HIPCHK(pp::launch_tile_pass(c->d_pass, grp, P.k, c->dbytes, c->track != 0, s));
     }
     {
         ProfScope ps(PC_READOUT, s);
@@ -533,18 +573,56 @@ void pp_circuit_destroy(pp_circuit *c) {
     delete c;
 }
 
-pp_status pp_circuit_load_gates(pp_circuit *c, int64_t m, const uint8_t *op, const int32_t *q0, const int32_t *q1,
+static pp_status validate_gates(int n, int64_t m, const uint8_t *op, const int32_t *q0, const int32_t *q1,
                                 const int32_t *param, int32_t n_params) {
-    if (!c) return fail(PP_ERR_INVALID, "null circuit");
     if (m < 0 || n_params < 0) return fail(PP_ERR_INVALID, "negative size");
     if (m > 0 && (!op || !q0 || !q1 || !param)) return fail(PP_ERR_INVALID, "null gate array");
     for (int64_t g = 0; g < m; ++g) {
         if (op[g] > PP_RZ) return fail(PP_ERR_INVALID, "unknown op at gate " + std::to_string(g));
-        if (q0[g] < 0 || q0[g] >= c->n) return fail(PP_ERR_INVALID, "qubit out of range at gate " + std::to_string(g));
-        if (op[g] == PP_CX && (q1[g] < 0 || q1[g] >= c->n || q1[g] == q0[g]))
+        if (q0[g] < 0 || q0[g] >= n) return fail(PP_ERR_INVALID, "qubit out of range at gate " + std::to_string(g));
+        if (op[g] == PP_CX && (q1[g] < 0 || q1[g] >= n || q1[g] == q0[g]))
             return fail(PP_ERR_INVALID, "bad CX target at gate " + std::to_string(g));
         if (op[g] >= PP_RX && (param[g] < 0 || param[g] >= n_params))
             return fail(PP_ERR_INVALID, "parameter index out of range at gate " + std::to_string(g));
+    }
+    return PP_OK;
+}
+
+pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *op, const int32_t *q0, const int32_t *q1,
+                             const int32_t *param, int32_t n_params, int32_t k, int32_t compose, int32_t reorder,
+                             int64_t *n_ops, int64_t *n_passes, int32_t *pass_ops, int64_t max_passes) {
+    if (n_qubits < 1 || n_qubits > kDenseMaxN) return fail(PP_ERR_INVALID, "n_qubits must be in [1, 16]");
+    if (k != n_qubits && (k < kLowQubits + 2 || k > 7 || k >= n_qubits))
+        return fail(PP_ERR_INVALID, "k must be n or in [4, min(7, n-1)]");
+    if (!n_ops || !n_passes || (max_passes > 0 && !pass_ops)) return fail(PP_ERR_INVALID, "null output");
+    pp_status r = validate_gates(n_qubits, m, op, q0, q1, param, n_params);
+    if (r != PP_OK) return r;
+    pp::GateList g;
+    g.n = n_qubits;
+    g.m = m;
+    g.op.assign(op, op + m);
+    g.q0.assign(q0, q0 + m);
+    g.q1.resize(m);
+    g.param.resize(m);
+    for (int64_t i = 0; i < m; ++i) {
+        g.q1[i] = op[i] == PP_CX ? q1[i] : -1;
+        g.param[i] = op[i] >= PP_RX ? param[i] : -1;
+    }
+    g.n_params = n_params;
+    pp::DensePlan P = pp::plan_dense(g, k, kLowQubits, compose != 0, reorder != 0);
+    *n_ops = (int64_t)P.ops.size();
+    *n_passes = (int64_t)P.passes.size();
+    for (int64_t i = 0; i < max_passes && i < (int64_t)P.passes.size(); ++i)
+        pass_ops[i] = P.passes[i].op_end - P.passes[i].op_begin;
+    return PP_OK;
+}
+
+pp_status pp_circuit_load_gates(pp_circuit *c, int64_t m, const uint8_t *op, const int32_t *q0, const int32_t *q1,
+                                const int32_t *param, int32_t n_params) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    {
+        pp_status r = validate_gates(c->n, m, op, q0, q1, param, n_params);
+        if (r != PP_OK) return r;
     }
     if (c->engine == PP_ENGINE_DENSE && m > 0 && c->n > 32)
         return fail(PP_ERR_INVALID, "DENSE engine needs n <= 32");
@@ -829,7 +907,7 @@ struct BatchCache {
     size_t dcap = 0;
     Staging staging;
     hipEvent_t done = nullptr;
-    struct Launch { int kind; int group_n; int off; int nd; int nblocks; };
+    struct Launch { int kind; int group_n; int off; int nd; int nblocks; pp::TileGroups tg; };
     std::vector<Launch> launches;  // kind 0 compose, 1 resident, 2 tile pass
     std::vector<int> tiled;        // indices of tiled circuits
     std::vector<int> single;       // indices evaluated one by one
@@ -885,7 +963,7 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
             else B.tiled.push_back((int)i);
         }
         if (!comp.empty())
-            B.launches.push_back({0, 0, append(comp.data(), comp.size() * sizeof(comp[0])), (int)comp.size(), 0});
+            B.launches.push_back({0, 0, append(comp.data(), comp.size() * sizeof(comp[0])), (int)comp.size(), 0, {}});
         // resident groups, largest size class first, longest circuits first
         for (int n = kResidentMaxN; n >= 1; --n) {
             auto &v = res_by_n[n];
@@ -898,9 +976,10 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
                 d.expval_out = d_expvals + i;
                 rd.push_back(d);
             }
-            B.launches.push_back({1, n, append(rd.data(), rd.size() * sizeof(rd[0])), (int)rd.size(), 0});
+            B.launches.push_back({1, n, append(rd.data(), rd.size() * sizeof(rd[0])), (int)rd.size(), 0, {}});
         }
-        // tiled circuits: pass l of every circuit that has one, per tile size
+        // tiled circuits: pass l of every circuit that has one, per tile size;
+        // within a launch, descriptors are grouped by tile count
         for (int k = 4; k <= 7; ++k) {
             std::vector<int> grp;
             size_t maxp = 0;
@@ -909,17 +988,35 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
                     grp.push_back(i);
                     maxp = std::max(maxp, cs[i]->dplan.passes.size());
                 }
+            std::stable_sort(grp.begin(), grp.end(), [&](int a, int b) { return cs[a]->n > cs[b]->n; });
             for (size_t l = 0; l < maxp; ++l) {
                 std::vector<pp::TilePassDesc> td;
-                int run = 0;
+                pp::TileGroups tg{};
+                int run = 0, last_n = -1;
                 for (int i : grp) {
                     if (l >= cs[i]->h_pass.size()) continue;
                     pp::TilePassDesc d = cs[i]->h_pass[l];
+                    if (d.n != last_n) {
+                        if (tg.ngroups == pp::kMaxTileGroups) {
+                            tg.first_block[tg.ngroups] = run;
+                            B.launches.push_back({2, k, append(td.data(), td.size() * sizeof(td[0])), (int)td.size(),
+                                                  run, tg});
+                            td.clear();
+                            tg = pp::TileGroups{};
+                            run = 0;
+                        }
+                        tg.first_block[tg.ngroups] = run;
+                        tg.first_desc[tg.ngroups] = (int32_t)td.size();
+                        tg.shift[tg.ngroups] = 2 * (d.n - k);
+                        tg.ngroups++;
+                        last_n = d.n;
+                    }
                     d.tile_begin = run;
                     run += d.ntiles;
                     td.push_back(d);
                 }
-                B.launches.push_back({2, k, append(td.data(), td.size() * sizeof(td[0])), (int)td.size(), run});
+                tg.first_block[tg.ngroups] = run;
+                B.launches.push_back({2, k, append(td.data(), td.size() * sizeof(td[0])), (int)td.size(), run, tg});
             }
         }
         if (blob.size() > B.dcap) {
@@ -947,8 +1044,7 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         } else if (L.kind == 1) {
             HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, s));
         } else {
-            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.nd, L.nblocks, L.group_n, dbytes,
-                                        false, s));
+            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.tg, L.group_n, dbytes, false, s));
         }
     }
     for (int i : B.tiled) {
@@ -968,10 +1064,179 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
     return PP_OK;
 }
 
+namespace {
+
+pp_status ensure_grad(pp_circuit *c, int64_t every) {
+    auto &G = c->gr;
+    if (G.valid && G.every == every) return PP_OK;
+    free_grad(c);
+    const int n = c->n;
+    const int k_heis = tile_qubits_for(c);
+    const int k_fwd = n <= 6 ? n : 6;
+    G.plan = pp::plan_gradient(c->g, k_heis, k_fwd, kLowQubits, every);
+    const pp::GradPlan &P = G.plan;
+    pp_status r;
+    if ((r = upload_vec(&G.hops, P.heis.ops)) != PP_OK) return r;
+    if ((r = upload_vec(&G.hroff, P.heis.roff)) != PP_OK) return r;
+    if ((r = upload_vec(&G.hrop, P.heis.rop)) != PP_OK) return r;
+    if ((r = upload_vec(&G.hrparam, P.heis.rparam)) != PP_OK) return r;
+    if ((r = upload_vec(&G.fops, P.fwd.ops)) != PP_OK) return r;
+    if ((r = upload_vec(&G.froff, P.fwd.roff)) != PP_OK) return r;
+    if ((r = upload_vec(&G.frop, P.fwd.rop)) != PP_OK) return r;
+    if ((r = upload_vec(&G.frparam, P.fwd.rparam)) != PP_OK) return r;
+    if ((r = upload_vec(&G.slot_param, P.slot_param)) != PP_OK) return r;
+    HIPCHK(dalloc(&G.hmaps, (size_t)9 * std::max(P.heis.nmaps(), 1)));
+    HIPCHK(dalloc(&G.fmaps, (size_t)9 * std::max(P.fwd.nmaps(), 1)));
+    std::vector<pp::ComposeDesc> comp;
+    if (P.heis.nmaps() > 0) comp.push_back({G.hroff, G.hrop, G.hrparam, c->d_theta, G.hmaps, P.heis.nmaps(), 0});
+    if (P.fwd.nmaps() > 0) comp.push_back({G.froff, G.frop, G.frparam, c->d_theta, G.fmaps, P.fwd.nmaps(), 0});
+    G.ncomp = (int)comp.size();
+    if ((r = upload_vec(&G.comp, comp)) != PP_OK) return r;
+    const size_t S = P.bounds.size() - 1;
+    const int64_t slots = dense_slots(n);
+    if (P.heis.resident) {
+        std::vector<pp::ResidentDesc> rd;
+        for (size_t sg = 0; sg < S; ++sg) {
+            const pp::DensePass &ps = P.heis.passes[P.heis_pass_begin[sg]];
+            pp::ResidentDesc d{};
+            d.coef_in = sg + 1 == S ? nullptr : c->coef;
+            d.coef_out = c->coef;
+            d.ops = G.hops + ps.op_begin;
+            d.maps = G.hmaps;
+            d.obs_x = c->d_ox;
+            d.obs_z = c->d_oz;
+            d.obs_c = c->d_oc;
+            d.expval_out = c->d_result;
+            d.counters = nullptr;
+            d.nops = ps.op_end - ps.op_begin;
+            d.n = n;
+            d.nterms = (int32_t)c->ox.size();
+            rd.push_back(d);
+        }
+        if ((r = upload_vec(&G.hres, rd)) != PP_OK) return r;
+    } else {
+        std::vector<pp::TilePassDesc> td;
+        for (const pp::DensePass &ps : P.heis.passes) {
+            pp::TilePassDesc d{};
+            d.coef = c->coef;
+            d.ops = G.hops;
+            d.maps = G.hmaps;
+            d.n = n;
+            d.k = k_heis;
+            d.op_begin = ps.op_begin;
+            d.op_end = ps.op_end;
+            d.ntiles = (int)((int64_t)1 << (2 * (n - k_heis)));
+            for (int j = 0; j < k_heis; ++j) d.qubits |= (uint64_t)ps.qubit[j] << (8 * j);
+            td.push_back(d);
+        }
+        if ((r = upload_vec(&G.hpass, td)) != PP_OK) return r;
+    }
+    HIPCHK(dalloc(&G.ckpt, (size_t)slots * std::max<size_t>(S, 1)));
+    HIPCHK(dalloc(&G.rbuf, (size_t)slots));
+    const int ntiles_f = (int)((int64_t)1 << (2 * (n - k_fwd)));
+    int max_seg = 1;
+    for (size_t sg = 0; sg < S; ++sg) max_seg = std::max(max_seg, P.seg_slot_begin[sg + 1] - P.seg_slot_begin[sg]);
+    HIPCHK(dalloc(&G.partials, (size_t)max_seg * ntiles_f));
+    HIPCHK(dalloc(&G.rot_grad, (size_t)std::max<size_t>(P.slot_param.size(), 1)));
+    std::vector<pp::GradPassDesc> gd;
+    for (size_t sg = 0; sg < S; ++sg)
+        for (int p = P.fwd_pass_begin[sg]; p < P.fwd_pass_begin[sg + 1]; ++p) {
+            const pp::DensePass &ps = P.fwd.passes[p];
+            pp::GradPassDesc d{};
+            d.c = (double *)c->coef;
+            d.r = G.rbuf;
+            d.ops = G.fops;
+            d.maps = G.fmaps;
+            d.partials = G.partials;
+            d.n = n;
+            d.k = k_fwd;
+            d.op_begin = ps.op_begin;
+            d.op_end = ps.op_end;
+            d.ntiles = ntiles_f;
+            d.slot_base = P.seg_slot_begin[sg];
+            for (int j = 0; j < k_fwd; ++j) d.qubits |= (uint64_t)ps.qubit[j] << (8 * j);
+            gd.push_back(d);
+        }
+    if ((r = upload_vec(&G.gpass, gd)) != PP_OK) return r;
+    G.k_heis = k_heis;
+    G.k_fwd = k_fwd;
+    G.every = every;
+    G.valid = true;
+    return PP_OK;
+}
+
+}  // namespace
+
 extern "C" pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_every_gates, double *d_expval,
                                  double *d_grad) {
-    (void)c; (void)stream; (void)checkpoint_every_gates; (void)d_expval; (void)d_grad;
-    return fail(PP_ERR_STATE, "gradient: not available in this build");
+    pp_status r = check_ready(c);
+    if (r != PP_OK) return r;
+    if (!d_expval || (c->g.n_params > 0 && !d_grad)) return fail(PP_ERR_INVALID, "null output");
+    if (checkpoint_every_gates < 0) return fail(PP_ERR_INVALID, "checkpoint_every_gates must be >= 0");
+    if (c->engine != PP_ENGINE_DENSE) return fail(PP_ERR_INVALID, "pp_gradient needs the DENSE engine");
+    if (c->dtype != PP_F64) return fail(PP_ERR_INVALID, "pp_gradient needs FP64 weights");
+    if ((r = ensure_plan(c)) != PP_OK) return r;
+    const int64_t every = checkpoint_every_gates > 0 ? checkpoint_every_gates : 256;
+    if ((r = ensure_grad(c, every)) != PP_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    auto &G = c->gr;
+    const pp::GradPlan &P = G.plan;
+    const int n = c->n;
+    const size_t S = P.bounds.size() - 1;
+    const int64_t slots = dense_slots(n);
+    double *coef = (double *)c->coef;
+    if (G.ncomp > 0) {
+        ProfScope ps(PC_COMPOSE, s);
+        HIPCHK(pp::launch_compose(G.comp, G.ncomp, s));
+    }
+    // Heisenberg sweep, last segment first; checkpoint c(O_b) at every
+    // segment start b
+    for (size_t sg = S; sg-- > 0;) {
+        if (P.heis.resident) {
+            ProfScope ps(PC_RES, s);
+            HIPCHK(pp::launch_resident(G.hres + sg, 1, n, 8, false, s));
+        } else {
+            if (sg + 1 == S) {
+                ProfScope ps(PC_INIT, s);
+                HIPCHK(pp::launch_dense_init(c->coef, nullptr, n, 8, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+            }
+            const int shift = 2 * (n - G.k_heis);
+            for (int p = P.heis_pass_begin[sg]; p < P.heis_pass_begin[sg + 1]; ++p) {
+                pp::TileGroups grp{};
+                grp.ngroups = 1;
+                grp.first_block[1] = 1 << shift;
+                grp.first_desc[0] = p;
+                grp.shift[0] = shift;
+                ProfScope ps(PC_TILE, s);
+                HIPCHK(pp::launch_tile_pass(G.hpass, grp, G.k_heis, 8, false, s));
+            }
+        }
+        if (sg > 0) HIPCHK(pp::launch_copy_f64(coef, G.ckpt + (size_t)sg * slots, slots, s));
+    }
+    {
+        ProfScope ps(PC_READOUT, s);
+        HIPCHK(pp::launch_dense_readout(c->coef, n, 8, d_expval, s));
+    }
+    // forward sweep of (c, r) with the joins of every rotation
+    HIPCHK(pp::launch_grad_init_state(G.rbuf, n, s));
+    const int ntiles_f = (int)((int64_t)1 << (2 * (n - G.k_fwd)));
+    int gp = 0;
+    for (size_t sg = 0; sg < S; ++sg) {
+        if (sg > 0) HIPCHK(pp::launch_copy_f64(G.ckpt + (size_t)sg * slots, coef, slots, s));
+        for (int p = P.fwd_pass_begin[sg]; p < P.fwd_pass_begin[sg + 1]; ++p, ++gp) {
+            ProfScope ps(PC_TILE, s);
+            HIPCHK(pp::launch_grad_pass(G.gpass + gp, ntiles_f, G.k_fwd, s));
+        }
+        const int nsl = P.seg_slot_begin[sg + 1] - P.seg_slot_begin[sg];
+        HIPCHK(pp::launch_grad_reduce(G.partials, nsl, ntiles_f, G.rot_grad + P.seg_slot_begin[sg], s));
+    }
+    if (c->g.n_params > 0)
+        HIPCHK(pp::launch_grad_accumulate(G.rot_grad, G.slot_param, (int)P.slot_param.size(), d_grad, c->g.n_params,
+                                          s));
+    fill_plan_stats(c);
+    c->evaluated = false;  // the dense weights now hold the forward-swept set
+    c->last_stream = s;
+    return PP_OK;
 }
 
 extern "C" pp_status pp_profile_enable(int32_t on) {

@@ -50,6 +50,16 @@ __device__ __forceinline__ long long zonly_slot(long long j, int n) {
     return s;
 }
 
+// Global slot offset of the local tile index i: local digit j goes to the
+// digit of global qubit (qubits >> 8j) & 0xff.  Digits [j0, k) only.
+__device__ __forceinline__ long long deposit_digits(int i, uint64_t qubits, int j0, int k) {
+    long long g = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j >= j0 && j < k) g |= (long long)((i >> (2 * j)) & 3) << (2 * (int)((qubits >> (8 * j)) & 0xff));
+    return g;
+}
+
 template <int BLOCK>
 __device__ double block_sum_d(double v, double *red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -76,34 +86,51 @@ __device__ long long block_sum_i(long long v, long long *red) {
 
 // ----------------------------------------------------------------- U1 op
 // Quad u of digit a: the slots base + d * 4^a, d = 0..3, with base the index
-// u with a zero digit inserted at position a.  Returns the number of
-// strings created (tracked runs only).
-template <typename T, bool TRACK>
-__device__ __forceinline__ int u1_apply(T *lc, uint8_t *lp, int k, int a, const double *__restrict__ M,
-                                        unsigned smask, int tid, int nthr) {
-    const int nq = 1 << (2 * (k - 1));
+// u with a zero digit inserted at position a.  K (tile digits) and BLOCK are
+// compile-time, so each thread's quads are loaded together before any store
+// (quads are disjoint).  Returns the number of strings created (tracked runs).
+template <typename T, bool TRACK, int K, int BLOCK>
+__device__ __forceinline__ int u1_apply(T *lc, uint8_t *lp, int a, const double *__restrict__ M, unsigned smask,
+                                        int tid) {
+    constexpr int NQ = 1 << (2 * (K - 1));
+    constexpr int QPT = NQ >= BLOCK ? NQ / BLOCK : 1;
     const int sh = 2 * a;
     const int lowmask = (1 << sh) - 1;
     const double m00 = M[0], m01 = M[1], m02 = M[2];
     const double m10 = M[3], m11 = M[4], m12 = M[5];
     const double m20 = M[6], m21 = M[7], m22 = M[8];
-    int delta = 0;
-    for (int u = tid; u < nq; u += nthr) {
+    if (NQ < BLOCK && tid >= NQ) return 0;
+    int iX[QPT], iY[QPT], iZ[QPT];
+    double cx[QPT], cy[QPT], cz[QPT];
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int u = tid + j * BLOCK;
         const int base = ((u & ~lowmask) << 2) | (u & lowmask);
-        const int iX = base | (1 << sh), iZ = base | (2 << sh), iY = base | (3 << sh);
-        const double cx = lds_ld(lc, iX), cy = lds_ld(lc, iY), cz = lds_ld(lc, iZ);
-        lds_st(lc, iX, m00 * cx + m01 * cy + m02 * cz);
-        lds_st(lc, iY, m10 * cx + m11 * cy + m12 * cz);
-        lds_st(lc, iZ, m20 * cx + m21 * cy + m22 * cz);
-        if (TRACK) {
-            const unsigned old = (unsigned)lp[sw(iX)] | ((unsigned)lp[sw(iY)] << 1) | ((unsigned)lp[sw(iZ)] << 2);
+        iX[j] = sw(base | (1 << sh));
+        iZ[j] = sw(base | (2 << sh));
+        iY[j] = sw(base | (3 << sh));
+        cx[j] = (double)lc[iX[j]];
+        cy[j] = (double)lc[iY[j]];
+        cz[j] = (double)lc[iZ[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        lc[iX[j]] = (T)(m00 * cx[j] + m01 * cy[j] + m02 * cz[j]);
+        lc[iY[j]] = (T)(m10 * cx[j] + m11 * cy[j] + m12 * cz[j]);
+        lc[iZ[j]] = (T)(m20 * cx[j] + m21 * cy[j] + m22 * cz[j]);
+    }
+    int delta = 0;
+    if (TRACK) {
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const unsigned old = (unsigned)lp[iX[j]] | ((unsigned)lp[iY[j]] << 1) | ((unsigned)lp[iZ[j]] << 2);
             unsigned nw = 0;
 #pragma unroll
             for (int r = 0; r < 3; ++r)
                 if ((smask >> (3 * r)) & 7u & old) nw |= 1u << r;
-            lp[sw(iX)] = (uint8_t)(nw & 1u);
-            lp[sw(iY)] = (uint8_t)((nw >> 1) & 1u);
-            lp[sw(iZ)] = (uint8_t)((nw >> 2) & 1u);
+            lp[iX[j]] = (uint8_t)(nw & 1u);
+            lp[iY[j]] = (uint8_t)((nw >> 1) & 1u);
+            lp[iZ[j]] = (uint8_t)((nw >> 2) & 1u);
             delta += __popc(nw) - __popc(old);
         }
     }
@@ -114,60 +141,114 @@ __device__ __forceinline__ int u1_apply(T *lc, uint8_t *lp, int k, int a, const 
 // Group u of digits (a = control, b = target): the 16 slots base + dc*4^a +
 // dt*4^b.  CX conjugation maps (xc, zc, xt, zt) to (xc, zc^zt, xt^xc, zt)
 // with a sign flip iff xc & zt & !(xt ^ zc); the map is an involution, so
-// the 12 moving slots form 6 signed swaps.
-template <typename T, bool TRACK>
-__device__ __forceinline__ void cx_apply(T *lc, uint8_t *lp, int k, int a, int b, int tid, int nthr) {
-    const int ng = 1 << (2 * (k - 2));
+// the 12 moving slots form 6 signed swaps.  Work item w = pair * NG + group,
+// so every thread gets the same number of swaps.
+struct CxPair { int dc1, dt1, dc2, dt2, neg; };
+__device__ __forceinline__ CxPair cx_pair(int p) {
+    // the six (control digit, target digit) pairs in ascending order of the
+    // first slot; digit value x + 2z
+    int found = 0;
+    CxPair out{0, 0, 0, 0, 0};
+#pragma unroll
+    for (int dc = 0; dc < 4; ++dc)
+#pragma unroll
+        for (int dt = 0; dt < 4; ++dt) {
+            const int xc = dc & 1, zc = dc >> 1, xt = dt & 1, zt = dt >> 1;
+            const int dc2 = xc | ((zc ^ zt) << 1), dt2 = (xt ^ xc) | (zt << 1);
+            if (dc2 * 4 + dt2 > dc * 4 + dt) {
+                if (found == p) out = CxPair{dc, dt, dc2, dt2, xc & zt & ((xt ^ zc) ^ 1)};
+                ++found;
+            }
+        }
+    return out;
+}
+
+template <typename T, bool TRACK, int K, int BLOCK>
+__device__ __forceinline__ void cx_apply(T *lc, uint8_t *lp, int a, int b, int tid) {
+    constexpr int NG = 1 << (2 * (K - 2));
+    constexpr int NW = 6 * NG;
+    constexpr int WPT = (NW + BLOCK - 1) / BLOCK;
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     const int mlo = (1 << (2 * lo)) - 1, mhi = (1 << (2 * hi)) - 1;
     const int sa = 2 * a, sb = 2 * b;
-    for (int u = tid; u < ng; u += nthr) {
+    int i1[WPT], i2[WPT];
+    bool neg[WPT], live[WPT];
+    double v1[WPT], v2[WPT];
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        const int w = tid + j * BLOCK;
+        live[j] = (NW % BLOCK == 0) || w < NW;
+        const int u = w & (NG - 1);
+        const CxPair pr = cx_pair(w / NG);
         int v = ((u & ~mlo) << 2) | (u & mlo);
         v = ((v & ~mhi) << 2) | (v & mhi);
+        i1[j] = sw(v | (pr.dc1 << sa) | (pr.dt1 << sb));
+        i2[j] = sw(v | (pr.dc2 << sa) | (pr.dt2 << sb));
+        neg[j] = pr.neg;
+        if (live[j]) {
+            v1[j] = (double)lc[i1[j]];
+            v2[j] = (double)lc[i2[j]];
+        }
+    }
 #pragma unroll
-        for (int dc = 0; dc < 4; ++dc) {
-#pragma unroll
-            for (int dt = 0; dt < 4; ++dt) {
-                const int xc = dc & 1, zc = dc >> 1, xt = dt & 1, zt = dt >> 1;
-                const int dc2 = xc | ((zc ^ zt) << 1), dt2 = (xt ^ xc) | (zt << 1);
-                if (dc2 * 4 + dt2 > dc * 4 + dt) {
-                    const bool neg = xc & zt & ((xt ^ zc) ^ 1);
-                    const int i1 = v | (dc << sa) | (dt << sb);
-                    const int i2 = v | (dc2 << sa) | (dt2 << sb);
-                    const double v1 = lds_ld(lc, i1), v2 = lds_ld(lc, i2);
-                    lds_st(lc, i1, neg ? -v2 : v2);
-                    lds_st(lc, i2, neg ? -v1 : v1);
-                    if (TRACK) {
-                        const uint8_t p1 = lp[sw(i1)], p2 = lp[sw(i2)];
-                        lp[sw(i1)] = p2;
-                        lp[sw(i2)] = p1;
-                    }
-                }
-            }
+    for (int j = 0; j < WPT; ++j) {
+        if (!live[j]) continue;
+        lc[i1[j]] = (T)(neg[j] ? -v2[j] : v2[j]);
+        lc[i2[j]] = (T)(neg[j] ? -v1[j] : v1[j]);
+        if (TRACK) {
+            const uint8_t p1 = lp[i1[j]], p2 = lp[i2[j]];
+            lp[i1[j]] = p2;
+            lp[i2[j]] = p1;
         }
     }
 }
 
-// Applies ops [o0, o1) to an LDS tile of 4^k slots.  For tracked runs it
+// Ops and their maps are staged through LDS in chunks: one cooperative load
+// per chunk instead of a dependent global load per op.
+constexpr int OPCH = 32;
+struct OpCache {
+    DOp ops[OPCH];
+    double maps[OPCH][9];
+};
+
+// Applies ops [o0, o1) to an LDS tile of 4^K slots.  For tracked runs it
 // accumulates term updates: every op adds ngates * (strings in the tile
 // before it), and U1 ops that can create strings update that count.
-template <typename T, bool TRACK, int BLOCK>
-__device__ void run_ops(T *lc, uint8_t *lp, int k, const DOp *__restrict__ ops, const double *__restrict__ maps,
-                        int o0, int o1, long long &tcount, long long &updates, long long *redi) {
+template <typename T, bool TRACK, int K, int BLOCK>
+__device__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const double *__restrict__ maps, int o0,
+                        int o1, long long &tcount, long long &updates, long long *redi, OpCache *oc) {
     const int tid = threadIdx.x;
-    for (int o = o0; o < o1; ++o) {
-        const DOp op = ops[o];
-        if (op.kind == DOP_U1) {
-            const int delta = u1_apply<T, TRACK>(lc, lp, k, op.a, maps + 9ull * op.map, op.smask, tid, BLOCK);
-            if (TRACK) {
-                updates += tcount * op.ngates;
-                if (!op.perm) tcount += block_sum_i<BLOCK>(delta, redi);
+    for (int cb = o0; cb < o1; cb += OPCH) {
+        const int cn = (o1 - cb) < OPCH ? (o1 - cb) : OPCH;
+        __syncthreads();
+        if (tid < cn) {
+            const DOp op = ops[cb + tid];
+            oc->ops[tid] = op;
+            if (op.kind == DOP_U1) {
+                const double *src = maps + 9ull * op.map;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) oc->maps[tid][j] = src[j];
             }
-        } else {
-            cx_apply<T, TRACK>(lc, lp, k, op.a, op.b, tid, BLOCK);
-            if (TRACK) updates += tcount * op.ngates;
         }
         __syncthreads();
+        for (int i = 0; i < cn; ++i) {
+            // op fields are the same for every lane: keep them in SGPRs
+            const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[0]);
+            const uint32_t w1 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[1]);
+            const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, b = (w0 >> 16) & 0xff, ngates = (w0 >> 24) & 0xff;
+            const unsigned smask = w1 & 0xffff, perm = w1 >> 16;
+            if (kind == DOP_U1) {
+                const int delta = u1_apply<T, TRACK, K, BLOCK>(lc, lp, a, oc->maps[i], smask, tid);
+                if (TRACK) {
+                    updates += tcount * ngates;
+                    if (!perm) tcount += block_sum_i<BLOCK>(delta, redi);
+                }
+            } else {
+                if constexpr (K >= 2) cx_apply<T, TRACK, K, BLOCK>(lc, lp, a, b, tid);
+                if (TRACK) updates += tcount * ngates;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -175,14 +256,15 @@ __device__ void run_ops(T *lc, uint8_t *lp, int k, const DOp *__restrict__ ops, 
 // One workgroup runs one whole circuit (n <= 7) in LDS: builds the
 // observable, applies every op, reads out <O> and optionally stores the
 // final weights / presence for pp_get_terms.
-template <typename T, bool TRACK, int BLOCK>
+template <typename T, bool TRACK, int N, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void resident_kernel(const ResidentDesc *__restrict__ descs) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double redd[BLOCK / 64];
     __shared__ long long redi[BLOCK / 64];
-    const ResidentDesc &d = descs[blockIdx.x];
-    const int n = d.n;
-    const int size = 1 << (2 * n);
+    __shared__ OpCache oc;
+    const ResidentDesc d = descs[blockIdx.x];
+    constexpr int n = N;
+    constexpr int size = 1 << (2 * N);
     T *lc = reinterpret_cast<T *>(smem);
     uint8_t *lp = smem + (size_t)size * sizeof(T);
     const int tid = threadIdx.x;
@@ -192,7 +274,10 @@ __global__ __launch_bounds__(BLOCK) void resident_kernel(const ResidentDesc *__r
         if (TRACK) lp[i] = 0;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (d.coef_in) {
+        const T *in = reinterpret_cast<const T *>(d.coef_in);
+        for (int i = tid; i < size; i += BLOCK) lc[sw(i)] = in[i];
+    } else if (tid == 0) {
         for (int t = 0; t < d.nterms; ++t) {
             const int s = (int)morton_slot(d.obs_x[t], d.obs_z[t], n);
             lc[sw(s)] = (T)((double)lc[sw(s)] + d.obs_c[t]);
@@ -207,7 +292,7 @@ __global__ __launch_bounds__(BLOCK) void resident_kernel(const ResidentDesc *__r
         for (int i = tid; i < size; i += BLOCK) mine += lp[i];
         tcount = block_sum_i<BLOCK>(mine, redi);
     }
-    run_ops<T, TRACK, BLOCK>(lc, lp, n, d.ops, d.maps, 0, d.nops, tcount, updates, redi);
+    run_ops<T, TRACK, N, BLOCK>(lc, lp, d.ops, d.maps, 0, d.nops, tcount, updates, redi, &oc);
 
     double part = 0.0;
     for (int j = tid; j < (1 << n); j += BLOCK) part += lds_ld(lc, (int)zonly_slot(j, n));
@@ -233,25 +318,28 @@ __global__ __launch_bounds__(BLOCK) void resident_kernel(const ResidentDesc *__r
 // pass's k qubits with the other n-k digits fixed to the tile index.  Local
 // digit j is global qubit qubit[j] (ascending), so the leading local digits
 // that equal their qubit form contiguous runs in HBM.
-template <typename T, bool TRACK, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void tile_kernel(const TilePassDesc *__restrict__ descs, int ndescs) {
+template <typename T, bool TRACK, int K, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tile_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long redi[BLOCK / 64];
-    int lo = 0, hi = ndescs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (descs[mid].tile_begin <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
-    }
-    const TilePassDesc &d = descs[lo];
-    const long long tile = (long long)blockIdx.x - d.tile_begin;
-    const int k = d.k, n = d.n;
-    const int size = 1 << (2 * k);
+    __shared__ OpCache oc;
+    const int b = blockIdx.x;
+    int gi0 = 0;
+    while (gi0 + 1 < grp.ngroups && b >= grp.first_block[gi0 + 1]) ++gi0;
+    const int rel = b - grp.first_block[gi0];
+    const TilePassDesc d = descs[grp.first_desc[gi0] + (rel >> grp.shift[gi0])];
+    const long long tile = rel & ((1 << grp.shift[gi0]) - 1);
+    constexpr int k = K;
+    const int n = d.n;
+    constexpr int size = 1 << (2 * K);
     T *lc = reinterpret_cast<T *>(smem);
     uint8_t *lp = smem + (size_t)size * sizeof(T);
     const int tid = threadIdx.x;
 
     unsigned inmask = 0;
-    for (int j = 0; j < k; ++j) inmask |= 1u << d.qubit[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < k) inmask |= 1u << (unsigned)((d.qubits >> (8 * j)) & 0xff);
     long long base = 0;
     {
         long long t = tile;
@@ -261,14 +349,14 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(const TilePassDesc *__restr
             t >>= 2;
         }
     }
-    int jlow = 0;
-    while (jlow < k && d.qubit[jlow] == jlow) ++jlow;
-    const int lowmask = (1 << (2 * jlow)) - 1;
+    // local index i = tid + r * BLOCK; BLOCK = 4^4, so the thread supplies
+    // digits 0-3 and r the digits above
+    static_assert(BLOCK == 256, "tile kernel assumes 256 threads");
+    const long long toff = base | deposit_digits(tid, d.qubits, 0, k < 4 ? k : 4);
 
     T *g = reinterpret_cast<T *>(d.coef);
-    for (int i = tid; i < size; i += BLOCK) {
-        long long gi = base | (i & lowmask);
-        for (int j = jlow; j < k; ++j) gi |= (long long)((i >> (2 * j)) & 3) << (2 * d.qubit[j]);
+    for (int i = tid, r = 0; i < size; i += BLOCK, ++r) {
+        const long long gi = toff | deposit_digits(r << 8, d.qubits, 4, k);
         lc[sw(i)] = g[gi];
         if (TRACK) lp[sw(i)] = d.pres[gi];
     }
@@ -280,15 +368,143 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(const TilePassDesc *__restr
         for (int i = tid; i < size; i += BLOCK) mine += lp[i];
         tcount = block_sum_i<BLOCK>(mine, redi);
     }
-    run_ops<T, TRACK, BLOCK>(lc, lp, k, d.ops, d.maps, d.op_begin, d.op_end, tcount, updates, redi);
+    run_ops<T, TRACK, K, BLOCK>(lc, lp, d.ops, d.maps, d.op_begin, d.op_end, tcount, updates, redi, &oc);
 
-    for (int i = tid; i < size; i += BLOCK) {
-        long long gi = base | (i & lowmask);
-        for (int j = jlow; j < k; ++j) gi |= (long long)((i >> (2 * j)) & 3) << (2 * d.qubit[j]);
+    for (int i = tid, r = 0; i < size; i += BLOCK, ++r) {
+        const long long gi = toff | deposit_digits(r << 8, d.qubits, 4, k);
         g[gi] = lc[sw(i)];
         if (TRACK) d.pres[gi] = lp[sw(i)];
     }
     if (TRACK && tid == 0 && updates) atomicAdd(d.counters, (unsigned long long)updates);
+}
+
+// ------------------------------------------------------ adjoint sweep
+// Forward propagation of the observable weights c and the state
+// coefficients r through one pass.  U1 ops hold the Heisenberg matrix M of a
+// single gate; the forward map (Table I) is its transpose because the maps
+// are orthogonal.  For a rotation R_sigma(theta) the derivative of <O> is
+// c^T (0 + A_sigma) r taken just before the gate, where A_sigma = R'(0) is the
+// generator of the forward rotation on (X, Y, Z):
+//   RX: c_Z r_Y - c_Y r_Z,  RY: c_X r_Z - c_Z r_X,  RZ: c_Y r_X - c_X r_Y.
+template <int K, int BLOCK>
+__device__ double join_part(const double *lc, const double *lr, int a, int axis, int tid) {
+    constexpr int NQ = 1 << (2 * (K - 1));
+    const int sh = 2 * a;
+    const int lowmask = (1 << sh) - 1;
+    double acc = 0.0;
+    for (int u = tid; u < NQ; u += BLOCK) {
+        const int base = ((u & ~lowmask) << 2) | (u & lowmask);
+        const int iX = sw(base | (1 << sh)), iZ = sw(base | (2 << sh)), iY = sw(base | (3 << sh));
+        if (axis == 3) acc += lc[iZ] * lr[iY] - lc[iY] * lr[iZ];
+        else if (axis == 4) acc += lc[iX] * lr[iZ] - lc[iZ] * lr[iX];
+        else acc += lc[iY] * lr[iX] - lc[iX] * lr[iY];
+    }
+    return acc;
+}
+
+template <int K, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void grad_kernel(const GradPassDesc *__restrict__ desc) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double redd[BLOCK / 64];
+    __shared__ OpCache oc;
+    const GradPassDesc d = *desc;
+    constexpr int size = 1 << (2 * K);
+    double *lc = reinterpret_cast<double *>(smem);
+    double *lr = lc + size;
+    const int tid = threadIdx.x;
+    const long long tile = blockIdx.x;
+    unsigned inmask = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < K) inmask |= 1u << (unsigned)((d.qubits >> (8 * j)) & 0xff);
+    long long base = 0;
+    {
+        long long t = tile;
+        for (int q = 0; q < d.n; ++q) {
+            if ((inmask >> q) & 1u) continue;
+            base |= (t & 3ll) << (2 * q);
+            t >>= 2;
+        }
+    }
+    for (int i = tid; i < size; i += BLOCK) {
+        const long long gi = base | deposit_digits(i, d.qubits, 0, K);
+        lc[sw(i)] = d.c[gi];
+        lr[sw(i)] = d.r[gi];
+    }
+    for (int cb = d.op_begin; cb < d.op_end; cb += OPCH) {
+        const int cn = (d.op_end - cb) < OPCH ? (d.op_end - cb) : OPCH;
+        __syncthreads();
+        if (tid < cn) {
+            const DOp op = d.ops[cb + tid];
+            oc.ops[tid] = op;
+            if (op.kind == DOP_U1) {
+                const double *src = d.maps + 9ull * op.map;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) oc.maps[tid][j] = src[j];
+            }
+        }
+        __syncthreads();
+        for (int i = 0; i < cn; ++i) {
+            const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc.ops[i])[0]);
+            const uint32_t slot = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc.ops[i])[3]);
+            const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, b = (w0 >> 16) & 0xff;
+            if (kind == DOP_U1) {
+                if (b >= 3) {
+                    const double part = block_sum_d<BLOCK>(join_part<K, BLOCK>(lc, lr, a, b, tid), redd);
+                    if (tid == 0) d.partials[(long long)(slot - d.slot_base) * d.ntiles + tile] = part;
+                    __syncthreads();
+                }
+                const double *M = oc.maps[i];
+                const double Mt[9] = {M[0], M[3], M[6], M[1], M[4], M[7], M[2], M[5], M[8]};
+                u1_apply<double, false, K, BLOCK>(lc, nullptr, a, Mt, 0u, tid);
+                u1_apply<double, false, K, BLOCK>(lr, nullptr, a, Mt, 0u, tid);
+            } else {
+                if constexpr (K >= 2) {
+                    cx_apply<double, false, K, BLOCK>(lc, nullptr, a, b, tid);
+                    cx_apply<double, false, K, BLOCK>(lr, nullptr, a, b, tid);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < size; i += BLOCK) {
+        const long long gi = base | deposit_digits(i, d.qubits, 0, K);
+        d.c[gi] = lc[sw(i)];
+        d.r[gi] = lr[sw(i)];
+    }
+}
+
+// r of |0...0><0...0|: Tr(P rho) = 1 for strings of I and Z only, else 0
+__global__ void grad_init_state_kernel(double *r, int n, long long size) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < size;
+         i += (long long)gridDim.x * blockDim.x) {
+        bool zonly = true;
+        for (int q = 0; q < n; ++q) zonly = zonly && !((i >> (2 * q)) & 1);
+        r[i] = zonly ? 1.0 : 0.0;
+    }
+}
+
+__global__ void grad_reduce_kernel(const double *partials, int nslots, int ntiles, double *rot_grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nslots) return;
+    double s = 0.0;
+    for (int t = 0; t < ntiles; ++t) s += partials[(long long)j * ntiles + t];
+    rot_grad[j] = s;
+}
+
+// sequential so that gates sharing a parameter are summed in gate order
+__global__ void grad_accumulate_kernel(const double *rot_grad, const int32_t *slot_param, int nslots, double *grad,
+                                       int nparams) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int p = 0; p < nparams; ++p) grad[p] = 0.0;
+    for (int j = 0; j < nslots; ++j) grad[slot_param[j]] += rot_grad[j];
+}
+
+__global__ void copy_f64_n_kernel(const double *src, double *dst, long long count) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // ---------------------------------------------------------- map composer
@@ -431,9 +647,12 @@ __global__ __launch_bounds__(256) void compact_write_kernel(const T *coef, const
 
 // ------------------------------------------------------------ launchers
 int max_lds_bytes() {
+    static int cached = 0;
+    if (cached) return cached;
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 65536;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+    cached = v;
     return v;
 }
 
@@ -448,25 +667,37 @@ hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, bool TRACK, int BLOCK>
+template <typename T, bool TRACK, int N, int BLOCK>
 static hipError_t launch_res_t(const ResidentDesc *d, int nd, size_t lds, hipStream_t s) {
-    auto fn = resident_kernel<T, TRACK, BLOCK>;
-    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    auto fn = resident_kernel<T, TRACK, N, BLOCK>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           max_lds_bytes() - (int)kStaticLdsReserve);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
     hipLaunchKernelGGL(fn, dim3(nd), dim3(BLOCK), lds, s, d);
     return hipGetLastError();
 }
 
 template <typename T, bool TRACK>
 static hipError_t launch_res_b(const ResidentDesc *d, int nd, int n, size_t lds, hipStream_t s) {
-    if (n <= 3) return launch_res_t<T, TRACK, 64>(d, nd, lds, s);
-    if (n <= 5) return launch_res_t<T, TRACK, 256>(d, nd, lds, s);
-    return launch_res_t<T, TRACK, 512>(d, nd, lds, s);
+    switch (n) {
+    case 1: return launch_res_t<T, TRACK, 1, 64>(d, nd, lds, s);
+    case 2: return launch_res_t<T, TRACK, 2, 64>(d, nd, lds, s);
+    case 3: return launch_res_t<T, TRACK, 3, 64>(d, nd, lds, s);
+    case 4: return launch_res_t<T, TRACK, 4, 64>(d, nd, lds, s);
+    case 5: return launch_res_t<T, TRACK, 5, 256>(d, nd, lds, s);
+    case 6: return launch_res_t<T, TRACK, 6, 256>(d, nd, lds, s);
+    default: return launch_res_t<T, TRACK, 7, 512>(d, nd, lds, s);
+    }
 }
 
 hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int dtype_bytes, bool track,
                            hipStream_t s) {
     if (ndescs <= 0) return hipSuccess;
+    if (n < 1 || n > 7) return hipErrorInvalidValue;
     const size_t lds = resident_lds_bytes(n, dtype_bytes, track);
     if (dtype_bytes == 8)
         return track ? launch_res_b<double, true>(d_descs, ndescs, n, lds, s)
@@ -475,24 +706,94 @@ hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int d
                  : launch_res_b<float, false>(d_descs, ndescs, n, lds, s);
 }
 
-template <typename T, bool TRACK, int BLOCK>
-static hipError_t launch_tile_t(const TilePassDesc *d, int nd, int nblocks, size_t lds, hipStream_t s) {
-    auto fn = tile_kernel<T, TRACK, BLOCK>;
-    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(nblocks), dim3(BLOCK), lds, s, d, nd);
+template <typename T, bool TRACK, int K>
+static hipError_t launch_tile_t(const TilePassDesc *d, const TileGroups &grp, size_t lds, hipStream_t s) {
+    auto fn = tile_kernel<T, TRACK, K, 256>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           max_lds_bytes() - (int)kStaticLdsReserve);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int nblocks = grp.first_block[grp.ngroups];
+    hipLaunchKernelGGL(fn, dim3(nblocks), dim3(256), lds, s, d, grp);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_pass(const TilePassDesc *d_descs, int ndescs, int nblocks, int k, int dtype_bytes,
-                            bool track, hipStream_t s) {
-    if (ndescs <= 0 || nblocks <= 0) return hipSuccess;
+template <typename T, bool TRACK>
+static hipError_t launch_tile_k(const TilePassDesc *d, const TileGroups &grp, int k, size_t lds, hipStream_t s) {
+    switch (k) {
+    case 4: return launch_tile_t<T, TRACK, 4>(d, grp, lds, s);
+    case 5: return launch_tile_t<T, TRACK, 5>(d, grp, lds, s);
+    case 6: return launch_tile_t<T, TRACK, 6>(d, grp, lds, s);
+    default: return launch_tile_t<T, TRACK, 7>(d, grp, lds, s);
+    }
+}
+
+hipError_t launch_tile_pass(const TilePassDesc *d_descs, const TileGroups &grp, int k, int dtype_bytes, bool track,
+                            hipStream_t s) {
+    if (grp.ngroups <= 0 || grp.first_block[grp.ngroups] <= 0) return hipSuccess;
+    if (k < 4 || k > 7) return hipErrorInvalidValue;
     const size_t lds = resident_lds_bytes(k, dtype_bytes, track);
     if (dtype_bytes == 8)
-        return track ? launch_tile_t<double, true, 256>(d_descs, ndescs, nblocks, lds, s)
-                     : launch_tile_t<double, false, 256>(d_descs, ndescs, nblocks, lds, s);
-    return track ? launch_tile_t<float, true, 256>(d_descs, ndescs, nblocks, lds, s)
-                 : launch_tile_t<float, false, 256>(d_descs, ndescs, nblocks, lds, s);
+        return track ? launch_tile_k<double, true>(d_descs, grp, k, lds, s)
+                     : launch_tile_k<double, false>(d_descs, grp, k, lds, s);
+    return track ? launch_tile_k<float, true>(d_descs, grp, k, lds, s)
+                 : launch_tile_k<float, false>(d_descs, grp, k, lds, s);
+}
+
+template <int K, int BLOCK>
+static hipError_t launch_grad_t(const GradPassDesc *d, int ntiles, hipStream_t s) {
+    auto fn = grad_kernel<K, BLOCK>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           max_lds_bytes() - (int)kStaticLdsReserve);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const size_t lds = 2 * sizeof(double) * ((size_t)1 << (2 * K));
+    hipLaunchKernelGGL(fn, dim3(ntiles), dim3(BLOCK), lds, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_pass(const GradPassDesc *d_desc, int ntiles, int k, hipStream_t s) {
+    switch (k) {
+    case 1: return launch_grad_t<1, 64>(d_desc, ntiles, s);
+    case 2: return launch_grad_t<2, 64>(d_desc, ntiles, s);
+    case 3: return launch_grad_t<3, 64>(d_desc, ntiles, s);
+    case 4: return launch_grad_t<4, 64>(d_desc, ntiles, s);
+    case 5: return launch_grad_t<5, 256>(d_desc, ntiles, s);
+    case 6: return launch_grad_t<6, 256>(d_desc, ntiles, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_grad_init_state(double *r, int n, hipStream_t s) {
+    const long long size = 1ll << (2 * n);
+    const int grid = (int)((size + 255) / 256 < 4096 ? (size + 255) / 256 : 4096);
+    hipLaunchKernelGGL(grad_init_state_kernel, dim3(grid), dim3(256), 0, s, r, n, size);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const double *partials, int nslots, int ntiles, double *rot_grad, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((nslots + 255) / 256), dim3(256), 0, s, partials, nslots, ntiles,
+                       rot_grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_accumulate(const double *rot_grad, const int32_t *slot_param, int nslots, double *grad,
+                                  int nparams, hipStream_t s) {
+    hipLaunchKernelGGL(grad_accumulate_kernel, dim3(1), dim3(64), 0, s, rot_grad, slot_param, nslots, grad, nparams);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double *src, double *dst, long long count, hipStream_t s) {
+    const int grid = (int)((count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096);
+    hipLaunchKernelGGL(copy_f64_n_kernel, dim3(grid), dim3(256), 0, s, src, dst, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_dense_init(void *coef, uint8_t *pres, int n, int dtype_bytes, const uint64_t *x,

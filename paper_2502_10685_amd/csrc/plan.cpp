@@ -48,14 +48,29 @@ unsigned smask_compose(unsigned after, unsigned before) {
 }
 
 DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder) {
+    PlanOptions o;
+    o.compose = compose;
+    o.reorder = reorder;
+    return plan_dense_opts(g, k, low, o);
+}
+
+DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &o) {
     DensePlan P;
     const int n = g.n;
+    const bool compose = o.compose, reorder = o.reorder;
     P.roff.push_back(0);
     P.k = k;
     P.resident = (k >= n);
-    const int64_t m = g.m;
-    // Heisenberg position h <-> gate index m-1-h
-    auto gate_of = [&](int64_t h) { return m - 1 - h; };
+    const int64_t gb = o.g_begin, ge = o.g_end < 0 ? g.m : o.g_end;
+    const int64_t m = ge - gb;
+    // position h in processing order <-> gate index
+    auto gate_of = [&](int64_t h) { return o.forward ? gb + h : ge - 1 - h; };
+    auto tag = [&](DOp &d, int64_t gi) {
+        if (o.slot && g.op[gi] >= 3) {
+            d.b = g.op[gi];
+            d.reserved = (uint32_t)(*o.slot)[gi];
+        }
+    };
 
     if (P.resident) {
         DensePass pass;
@@ -98,6 +113,7 @@ DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reord
                 d.smask = (uint16_t)gate_smask(op);
                 d.perm = rot ? 0 : 1;
                 d.map = (uint32_t)pend.size();
+                tag(d, gi);
                 pend.push_back({q, {{op, rot ? g.param[gi] : -1}}});
                 open[q] = (int)ops.size();
                 ops.push_back(d);
@@ -232,6 +248,7 @@ DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reord
                 d.smask = (uint16_t)gate_smask(op);
                 d.perm = rot ? 0 : 1;
                 d.map = (uint32_t)(map_base + pend.size());
+                tag(d, gi);
                 pend.push_back({{{op, rot ? g.param[gi] : -1}}});
                 open[dg] = (int)P.ops.size();
                 P.ops.push_back(d);
@@ -249,6 +266,68 @@ DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reord
         P.passes.push_back(pass);
     }
     return P;
+}
+
+void plan_append(DensePlan &all, const DensePlan &part) {
+    if (all.roff.empty()) all.roff.push_back(0);
+    const int op_off = (int)all.ops.size();
+    const uint32_t map_off = (uint32_t)all.nmaps();
+    const int32_t rec_off = (int32_t)all.rop.size();
+    for (DOp d : part.ops) {
+        if (d.kind == DOP_U1) d.map += map_off;
+        all.ops.push_back(d);
+    }
+    for (size_t i = 1; i < part.roff.size(); ++i) all.roff.push_back(part.roff[i] + rec_off);
+    all.rop.insert(all.rop.end(), part.rop.begin(), part.rop.end());
+    all.rparam.insert(all.rparam.end(), part.rparam.begin(), part.rparam.end());
+    for (DensePass ps : part.passes) {
+        ps.op_begin += op_off;
+        ps.op_end += op_off;
+        all.passes.push_back(ps);
+    }
+    all.k = part.k;
+    all.resident = part.resident;
+}
+
+GradPlan plan_gradient(const GateList &g, int k_heis, int k_fwd, int low, int64_t every) {
+    GradPlan G;
+    const int64_t m = g.m;
+    if (every <= 0) every = m > 0 ? m : 1;
+    for (int64_t b = 0; b < m; b += every) G.bounds.push_back(b);
+    G.bounds.push_back(m);
+    if (G.bounds.size() == 1) G.bounds.push_back(m);  // m == 0: one empty segment
+    std::vector<int32_t> slot(m, -1);
+    int32_t ns = 0;
+    const size_t S = G.bounds.size() - 1;
+    for (size_t s = 0; s < S; ++s) {
+        G.seg_slot_begin.push_back(ns);
+        for (int64_t gi = G.bounds[s]; gi < G.bounds[s + 1]; ++gi)
+            if (g.op[gi] >= 3) {
+                slot[gi] = ns++;
+                G.slot_param.push_back(g.param[gi]);
+            }
+    }
+    G.seg_slot_begin.push_back(ns);
+    G.heis.roff.push_back(0);
+    G.fwd.roff.push_back(0);
+    for (size_t s = 0; s < S; ++s) {
+        PlanOptions h;
+        h.g_begin = G.bounds[s];
+        h.g_end = G.bounds[s + 1];
+        G.heis_pass_begin.push_back((int)G.heis.passes.size());
+        plan_append(G.heis, plan_dense_opts(g, k_heis, low, h));
+        PlanOptions f;
+        f.compose = false;
+        f.forward = true;
+        f.g_begin = G.bounds[s];
+        f.g_end = G.bounds[s + 1];
+        f.slot = &slot;
+        G.fwd_pass_begin.push_back((int)G.fwd.passes.size());
+        plan_append(G.fwd, plan_dense_opts(g, k_fwd, low, f));
+    }
+    G.heis_pass_begin.push_back((int)G.heis.passes.size());
+    G.fwd_pass_begin.push_back((int)G.fwd.passes.size());
+    return G;
 }
 
 SparsePlan plan_sparse(const GateList &g) {

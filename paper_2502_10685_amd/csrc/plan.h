@@ -50,6 +50,34 @@ struct SparsePlan {
 // k == n: one resident pass; k < n: passes of k-qubit tiles that always
 // contain the lowest `low` qubits.
 DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder);
+
+// General form: gates [g_begin, g_end) only; forward = g_begin first (the
+// adjoint sweep) instead of Heisenberg order; slot (optional, size m): for
+// each rotation gate its join slot, stored in DOp::reserved with DOp::b set
+// to the rotation's op code.
+struct PlanOptions {
+    bool compose = true;
+    bool reorder = true;
+    bool forward = false;
+    int64_t g_begin = 0, g_end = -1;
+    const std::vector<int32_t> *slot = nullptr;
+};
+DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &o);
+
+// Appends `part` to `all`, offsetting op, map and recipe indices.
+void plan_append(DensePlan &all, const DensePlan &part);
+
+// Adjoint-gradient schedule: segments [bounds[s], bounds[s+1]) of the gate
+// list; Heisenberg plans per segment (composed) and forward per-gate plans
+// per segment; rotation slots in gate order.
+struct GradPlan {
+    std::vector<int64_t> bounds;
+    DensePlan heis, fwd;
+    std::vector<int> heis_pass_begin, fwd_pass_begin;  // S + 1 entries each
+    std::vector<int32_t> slot_param;                  // slot -> parameter
+    std::vector<int32_t> seg_slot_begin;              // S + 1 entries
+};
+GradPlan plan_gradient(const GateList &g, int k_heis, int k_fwd, int low, int64_t every);
 SparsePlan plan_sparse(const GateList &g);
 
 // structural 3x3 pattern of one gate's Heisenberg map (bit 3*row + col)

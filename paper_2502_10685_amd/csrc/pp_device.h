@@ -31,6 +31,7 @@ static_assert(sizeof(DOp) == 16, "DOp must stay 16 bytes");
 
 // A whole circuit run inside one workgroup's LDS (n <= 7).
 struct ResidentDesc {
+    const void *coef_in;       // start weights (4^n, slot order) or nullptr = the observable
     void *coef_out;            // final weights (4^n, slot order) or nullptr
     uint8_t *pres_out;         // final presence bytes or nullptr
     const DOp *ops;
@@ -56,7 +57,37 @@ struct TilePassDesc {
     int32_t op_begin, op_end;
     int32_t tile_begin;            // first block of this desc in the launch
     int32_t ntiles;
-    uint8_t qubit[8];              // global qubit of local digit j, ascending
+    uint64_t qubits;               // byte j = global qubit of local digit j (ascending)
+};
+
+// One pass of the adjoint sweep over tiles of 4^k slots (k = n: one tile).
+// c: the observable's weights, r: the Pauli coefficients Tr(P rho) of the
+// state, both FP64, both propagated forward through the pass's ops.  A U1 op
+// of a rotation (b = 3, 4, 5 for RX, RY, RZ) first writes the tile's share of
+// its join c^T A r to partials[(reserved - slot_base) * ntiles + tile].
+struct GradPassDesc {
+    double *c;
+    double *r;
+    const DOp *ops;
+    const double *maps;
+    double *partials;
+    int32_t n, k;
+    int32_t op_begin, op_end;
+    int32_t ntiles, slot_base;
+    uint64_t qubits;
+};
+
+// Block -> descriptor mapping of one tile-pass launch.  Descriptors are
+// grouped by tile count (a power of 4); group g covers blocks
+// [first_block[g], first_block[g+1]) and block b of it handles tile
+// (b - first_block[g]) & ((1 << shift[g]) - 1) of descriptor
+// first_desc[g] + ((b - first_block[g]) >> shift[g]).
+constexpr int kMaxTileGroups = 8;
+struct TileGroups {
+    int32_t ngroups;
+    int32_t first_block[kMaxTileGroups + 1];
+    int32_t first_desc[kMaxTileGroups];
+    int32_t shift[kMaxTileGroups];
 };
 
 // Per-circuit composition job: maps[i] = product of the gate matrices of
@@ -87,8 +118,14 @@ struct SparsePassDesc {
 hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s);
 hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int dtype_bytes, bool track,
                            hipStream_t s);
-hipError_t launch_tile_pass(const TilePassDesc *d_descs, int ndescs, int nblocks, int k, int dtype_bytes,
+hipError_t launch_tile_pass(const TilePassDesc *d_descs, const TileGroups &groups, int k, int dtype_bytes,
                             bool track, hipStream_t s);
+hipError_t launch_grad_pass(const GradPassDesc *d_desc, int ntiles, int k, hipStream_t s);
+hipError_t launch_grad_init_state(double *r, int n, hipStream_t s);
+hipError_t launch_grad_reduce(const double *partials, int nslots, int ntiles, double *rot_grad, hipStream_t s);
+hipError_t launch_grad_accumulate(const double *rot_grad, const int32_t *slot_param, int nslots, double *grad,
+                                  int nparams, hipStream_t s);
+hipError_t launch_copy_f64(const double *src, double *dst, long long count, hipStream_t s);
 hipError_t launch_dense_init(void *coef, uint8_t *pres, int n, int dtype_bytes, const uint64_t *x,
                              const uint64_t *z, const double *c, int nterms, hipStream_t s);
 hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double *out, hipStream_t s);
@@ -97,6 +134,7 @@ hipError_t launch_dense_compact(const void *coef, const uint8_t *pres, int n, in
                                 uint64_t *z, double *c, unsigned long long *count, int *tile_flags,
                                 unsigned long long *tile_vals, int *ticket, hipStream_t s);
 size_t resident_lds_bytes(int n, int dtype_bytes, bool track);
+constexpr size_t kStaticLdsReserve = 8192;  // op cache + reductions per workgroup
 int max_lds_bytes();
 
 // Sparse engine (sparse.hip)

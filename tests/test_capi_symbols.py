@@ -50,3 +50,32 @@ def test_version_and_null_safety_without_gpu():
 def test_stats_struct_layout_matches_header():
     from paper_2502_10685_amd import _lib as L
     assert ctypes.sizeof(L.PPStats) == 7 * 8 + 4 * 4
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpauliprop.so not built")
+def test_planner_host_logic():
+    """The DENSE scheduler, run on the host: one pass when the tile is the
+    whole register, every op counted once, composition only merges
+    single-qubit gates, tracked schedules keep one op per gate."""
+    import numpy as np
+    from paper_2502_10685_amd import _lib as L
+    from paper_2502_10685_amd import workloads as W
+    rng = np.random.default_rng(4)
+    w = W.random_circuit(rng, 9, 3000)
+    ncx = int(np.sum(w.op == 2))
+    ops, passes = L.plan_dense_info(9, w.op, w.q0, w.q1, w.param, w.n_params, 9)
+    assert passes == 1 and ncx < ops < w.m
+    ops_t, passes_t, per = L.plan_dense_info(9, w.op, w.q0, w.q1, w.param, w.n_params, 5, compose=False,
+                                             reorder=False, want_passes=True)
+    assert ops_t == w.m and per.sum() == w.m and len(per) == passes_t
+    ops_c, passes_c, per_c = L.plan_dense_info(9, w.op, w.q0, w.q1, w.param, w.n_params, 5, want_passes=True)
+    assert per_c.sum() == ops_c and ops_c < ops_t
+    assert passes_c < passes_t  # reordering packs more gates per tile pass
+    hea = W.config4()
+    ops_h, passes_h = L.plan_dense_info(8, hea.op, hea.q0, hea.q1, hea.param, hea.n_params, 8)
+    # per layer: 8 wires x (RX RY RZ) fold into 8 U1 ops, plus 8 CX
+    assert ops_h == 40 * 16
+    with pytest.raises(L.PauliPropError):
+        L.plan_dense_info(9, w.op, w.q0 + 20, w.q1, w.param, w.n_params, 5)
+    with pytest.raises(L.PauliPropError):
+        L.plan_dense_info(9, w.op, w.q0, w.q1, w.param, w.n_params, 3)
