@@ -54,21 +54,85 @@ def build_workload(name):
     return circs, desc
 
 
+def updates_of(api, w, dtype="f64"):
+    """U = sum over gates of the set size entering the gate, in Heisenberg
+    order (g_m first), from tracked GPU runs.  The set size never decreases
+    and is at most 4^n - 1 (+1 if O contains the identity), so a tracked run
+    over the last L gates that ends saturated fixes U exactly:
+    U = U_last_L + (m - L) * T_max.  L doubles until saturated or L = m."""
+    from paper_2502_10685_amd import workloads as W
+    n, m = w.n, w.m
+    ident = bool(np.any((w.obs_x == 0) & (w.obs_z == 0)))
+    tmax = 4 ** n - 1 + (1 if ident else 0)
+    L = min(m, 256)
+    while True:
+        sub = W.make_circuit(n, (w.op[m - L:], w.q0[m - L:], w.q1[m - L:], w.param[m - L:]), w.n_params,
+                             (w.obs_x, w.obs_z, w.obs_c), w.theta)
+        c = api.Circuit.from_workload(sub, dtype=dtype, track=True)
+        c.evaluate()
+        st = c.stats()
+        c.close()
+        if L == m:
+            return st["term_updates"], st["final_terms"]
+        if st["final_terms"] == tmax:
+            return st["term_updates"] + (m - L) * tmax, tmax
+        L = min(m, 2 * L)
+
+
 def count_updates(api, circs, dtype):
-    """U per circuit from one tracked GPU run each (structure only: U does not
-    depend on theta)."""
+    """U per circuit (structure only: U does not depend on theta)."""
     us, terms = [], []
     t0 = time.time()
     for i, w in enumerate(circs):
-        c = api.Circuit.from_workload(w, dtype=dtype, track=True)
-        c.evaluate()
-        st = c.stats()
-        us.append(st["term_updates"])
-        terms.append(st["final_terms"])
-        c.close()
+        u, t = updates_of(api, w, dtype)
+        us.append(u)
+        terms.append(t)
         if (i + 1) % 128 == 0:
-            log(f"tracked runs {i + 1}/{len(circs)} ({time.time() - t0:.1f}s)")
+            log(f"update counts {i + 1}/{len(circs)} ({time.time() - t0:.1f}s)")
     return np.array(us, dtype=np.int64), np.array(terms, dtype=np.int64)
+
+
+def serve(api, lam, count, budget, max_active):
+    """Poisson arrivals at rate lam (seeded) of random circuits n ~ U{4..12},
+    m log-uniform in [1k, 60k]; submit at arrival time, poll completions."""
+    from paper_2502_10685_amd import workloads as W
+    reqs = W.config5_requests(seed=5, lam=lam, count=count)
+    arrivals = np.array([a for a, _ in reqs])
+    ws = [w for _, w in reqs]
+    U, _ = count_updates(api, ws, "f64")
+    circs = [api.Circuit.from_workload(w) for w in ws]
+    srv = api.Server(mem_budget_bytes=budget, max_active=max_active)
+    import torch
+    torch.cuda.synchronize()
+    lat, done_at, vals = {}, {}, {}
+    t0 = time.perf_counter()
+    i = 0
+    tickets = {}
+    while len(done_at) < count:
+        now = time.perf_counter() - t0
+        while i < count and arrivals[i] <= now:
+            tickets[srv.submit(circs[i])] = i
+            i += 1
+        for t, j in list(tickets.items()):
+            r = srv.poll(t)
+            if r is not None:
+                vals[j], lat[j] = r
+                done_at[j] = time.perf_counter() - t0
+                del tickets[t]
+        if i < count:
+            time.sleep(max(0.0, min(5e-4, arrivals[i] - (time.perf_counter() - t0))))
+        else:
+            time.sleep(2e-4)
+    span = max(done_at.values())
+    cnt = srv.counters()
+    srv.close()
+    lats = np.array([lat[j] for j in range(count)]) * 1e-3
+    return {"lambda_per_s": lam, "requests": count, "span_s": span,
+            "offered_updates_per_s": float(U.sum() / max(arrivals[-1], 1e-9)),
+            "updates_per_s": float(U.sum() / span), "circuits_per_s": count / span,
+            "latency_ms": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99))},
+            "term_updates": int(U.sum()), "server": cnt,
+            "n_range": [int(min(w.n for w in ws)), int(max(w.n for w in ws))]}
 
 
 def timed_steps(fn, steps, torch):
@@ -136,6 +200,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -240,6 +306,15 @@ def main():
                        "max_abs_diff_vs_fp64": float(np.max(np.abs(v32 - gpu_vals)))}
         log(f"fp32: {s32 / args.steps * 1e3:.2f} ms/step")
         del objs32
+
+    if not args.no_serve and args.workload == "batch512":
+        res["serving"] = []
+        for lam in (100.0, 1000.0):
+            log(f"serving lambda={lam:.0f}/s")
+            sv = serve(api, lam, args.serve_requests, budget=64 << 30, max_active=64)
+            log(f"serving lambda={lam:.0f}: p50 {sv['latency_ms']['p50']:.1f} ms, p99 "
+                f"{sv['latency_ms']['p99']:.1f} ms, {sv['updates_per_s']:.3e} updates/s")
+            res["serving"].append(sv)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

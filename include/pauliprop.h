@@ -180,6 +180,43 @@ PP_API pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uin
  * stream of that evaluation). */
 PP_API pp_status pp_get_stats(pp_circuit *c, pp_stats *out);
 
+/* ----------------------------------------------------------- serving */
+typedef struct pp_server pp_server;
+
+/* Starts a serving loop on its own host thread and HIP streams of the
+ * current device.  Requests are admitted in arrival order while at most
+ * max_active are in flight and the sum of their term-buffer footprints
+ * (4^n weights for DENSE, the term capacity for SPARSE) stays within
+ * mem_budget_bytes.  Admitted requests share work: every loop iteration
+ * issues one batched tile pass holding the next pass of every active tiled
+ * request (requests join and leave between iterations), while circuits that
+ * fit one workgroup's LDS run whole on a second stream, overlapping the
+ * passes.  Each request's result is bit-identical to its own pp_evaluate. */
+PP_API pp_status pp_server_create(int64_t mem_budget_bytes, int32_t max_active, pp_server **out);
+
+/* Queues an evaluation of circuit c (gates, theta and observable set) and
+ * returns its ticket.  The server owns c until the request is done: the
+ * caller must not use or destroy it before pp_server_poll reports done.
+ * PP_ERR_CAPACITY if c alone exceeds the memory budget; PP_ERR_STATE after
+ * pp_server_destroy has begun. */
+PP_API pp_status pp_server_submit(pp_server *s, pp_circuit *c, int64_t *ticket);
+
+/* Non-blocking status of a ticket: *done = 1 once the result is on the
+ * host; then *expval is <O> and *latency_us the time from submission to
+ * completion seen by the serving thread.  A failed request reports done with
+ * its pp_status returned.  PP_ERR_INVALID for an unknown ticket. */
+PP_API pp_status pp_server_poll(pp_server *s, int64_t ticket, int32_t *done, double *expval, double *latency_us);
+
+/* Blocks until every submitted request is done. */
+PP_API pp_status pp_server_drain(pp_server *s);
+
+/* Loop iterations and batched tile launches issued so far. */
+PP_API pp_status pp_server_counters(pp_server *s, int64_t *iterations, int64_t *tile_launches, int64_t *max_in_flight);
+
+/* Finishes the queued requests, stops the loop and releases the server.
+ * NULL-safe. */
+PP_API void pp_server_destroy(pp_server *s);
+
 /* Host-only planning introspection (no device needed): runs the DENSE
  * scheduler on a gate list and reports the number of device ops and passes
  * for tiles of k qubits (k = n: one LDS-resident pass).  compose = fold a

@@ -64,6 +64,13 @@ def load():
         "pp_gradient": (st, [P, P, I32, P, P]),
         "pp_get_terms": (st, [P, P, I64, P, P, P, ctypes.POINTER(I64)]),
         "pp_get_stats": (st, [P, ctypes.POINTER(PPStats)]),
+        "pp_server_create": (st, [I64, I32, ctypes.POINTER(P)]),
+        "pp_server_submit": (st, [P, P, ctypes.POINTER(I64)]),
+        "pp_server_poll": (st, [P, I64, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]),
+        "pp_server_drain": (st, [P]),
+        "pp_server_counters": (st, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+        "pp_server_destroy": (None, [P]),
         "pp_plan_dense_info": (st, [I32, I64, P, P, P, P, I32, I32, I32, I32, ctypes.POINTER(I64),
                                     ctypes.POINTER(I64), P, I64]),
         "pp_profile_enable": (st, [I32]),

@@ -147,6 +147,57 @@ def evaluate_batch(circuits, out: torch.Tensor | None = None, stream=None) -> to
     return out
 
 
+class Server:
+    """Continuous-batching serving loop of the library (its own host thread
+    and streams).  submit() takes a prepared Circuit and returns a ticket;
+    poll() returns None until done, then (expval, latency_us)."""
+
+    def __init__(self, mem_budget_bytes=64 << 30, max_active=256):
+        _require_gpu()
+        self._lib = L.load()
+        h = ctypes.c_void_p()
+        L.check(self._lib.pp_server_create(int(mem_budget_bytes), int(max_active), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, circ: Circuit) -> int:
+        t = ctypes.c_int64(0)
+        L.check(self._lib.pp_server_submit(self._h, circ._h, ctypes.byref(t)))
+        self._keep[t.value] = circ
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int32(0)
+        ev = ctypes.c_double(0.0)
+        lat = ctypes.c_double(0.0)
+        L.check(self._lib.pp_server_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(ev),
+                                         ctypes.byref(lat)))
+        if not done.value:
+            return None
+        self._keep.pop(int(ticket), None)
+        return ev.value, lat.value
+
+    def drain(self):
+        L.check(self._lib.pp_server_drain(self._h))
+
+    def counters(self):
+        a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        L.check(self._lib.pp_server_counters(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"iterations": a.value, "tile_launches": b.value, "max_in_flight": c.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pp_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class _ExpvalFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, circ, checkpoint_every):

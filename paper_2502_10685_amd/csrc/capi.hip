@@ -8,9 +8,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/pauliprop.h"
@@ -1270,4 +1276,372 @@ extern "C" pp_status pp_profile_read(pp_kernel_time *out, int32_t max, int32_t *
     }
     *n_out = std::min(k, max);
     return PP_OK;
+}
+
+// ================================================================= serving
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t footprint_bytes(const pp_circuit *c) {
+    if (c->engine == PP_ENGINE_DENSE) return dense_slots(c->n) * c->dbytes;
+    const int64_t cap = c->max_terms > 0 ? c->max_terms : (c->n <= 12 ? dense_slots(c->n) : ((int64_t)1 << 24));
+    return 2 * cap * (16 + 2 * (int64_t)c->dbytes);
+}
+
+struct ServedReq {
+    int64_t ticket = 0;
+    pp_circuit *c = nullptr;
+    int state = 0;  // 0 queued, 1 admitted, 2 finishing, 3 done
+    bool prepared = false;
+    int64_t foot = 0;
+    double t_submit = 0, t_done = 0;
+    size_t pass = 0;
+    int slot = -1;
+    hipEvent_t ev = nullptr;
+    double result = 0;
+    pp_status status = PP_OK;
+};
+
+constexpr int kRing = 4;
+
+}  // namespace
+
+struct pp_server {
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::thread th;
+    bool stop = false;
+    std::deque<ServedReq *> queue;
+    std::vector<ServedReq *> active;
+    std::unordered_map<int64_t, ServedReq *> reqs;
+    int64_t next_ticket = 1;
+    int64_t budget = 0, used = 0;
+    int max_active = 0;
+    hipStream_t main = nullptr, side = nullptr;
+    double *d_results = nullptr, *h_results = nullptr;
+    std::vector<int> free_slots;
+    struct Ring {
+        void *d = nullptr, *h = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    } ring[kRing];
+    int ring_i = 0;
+    int64_t iterations = 0, tile_launches = 0, max_in_flight = 0;
+    int dev = 0;
+};
+
+namespace {
+
+pp_status ring_upload(pp_server *S, const std::vector<unsigned char> &blob, void **dptr) {
+    pp_server::Ring &R = S->ring[S->ring_i];
+    S->ring_i = (S->ring_i + 1) % kRing;
+    if (R.used) HIPCHK(hipEventSynchronize(R.ev));  // bounds how far the host runs ahead
+    if (blob.size() > R.cap) {
+        if (R.d) (void)hipFree(R.d);
+        if (R.h) (void)hipHostFree(R.h);
+        R.d = R.h = nullptr;
+        const size_t cap = std::max<size_t>(blob.size() * 2, 1 << 16);
+        HIPCHK(hipMalloc(&R.d, cap));
+        HIPCHK(hipHostMalloc(&R.h, cap, hipHostMallocDefault));
+        R.cap = cap;
+    }
+    std::memcpy(R.h, blob.data(), blob.size());
+    HIPCHK(hipMemcpyAsync(R.d, R.h, blob.size(), hipMemcpyHostToDevice, S->main));
+    if (!R.ev) HIPCHK(hipEventCreateWithFlags(&R.ev, hipEventDisableTiming));
+    *dptr = R.d;
+    return PP_OK;
+}
+
+void ring_mark(pp_server *S) {
+    pp_server::Ring &R = S->ring[(S->ring_i + kRing - 1) % kRing];
+    if (hipEventRecord(R.ev, S->main) == hipSuccess) R.used = true;
+}
+
+pp_status finish_async(pp_server *S, ServedReq *r, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(S->h_results + r->slot, S->d_results + r->slot, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (!r->ev) HIPCHK(hipEventCreateWithFlags(&r->ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(r->ev, st));
+    r->state = 2;
+    return PP_OK;
+}
+
+// Prepares an admitted request and starts what runs whole.
+pp_status start_request(pp_server *S, ServedReq *r) {
+    pp_circuit *c = r->c;
+    pp_status st = ensure_plan(c);
+    if (st != PP_OK) return st;
+    fill_plan_stats(c);
+    r->prepared = true;
+    double *out = S->d_results + r->slot;
+    if (c->engine != PP_ENGINE_DENSE || c->track || c->dplan.resident) {
+        st = pp_evaluate(c, S->side, out);
+        if (st != PP_OK) return st;
+        return finish_async(S, r, S->side);
+    }
+    if (c->dplan.nmaps() > 0) HIPCHK(pp::launch_compose(c->d_comp, 1, S->main));
+    HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(),
+                                 S->main));
+    r->pass = 0;
+    return PP_OK;
+}
+
+void complete(pp_server *S, ServedReq *r, pp_status st) {
+    r->status = st;
+    r->t_done = now_s();
+    if (st == PP_OK) r->result = S->h_results[r->slot];
+    r->state = 3;
+    r->c->evaluated = true;
+    r->c->last_track = r->c->track;
+    r->c->last_stream = r->c->engine == PP_ENGINE_DENSE && !r->c->track && !r->c->dplan.resident ? S->main : S->side;
+}
+
+void server_loop(pp_server *S) {
+    (void)hipSetDevice(S->dev);
+    std::vector<ServedReq *> fresh;
+    for (;;) {
+        fresh.clear();
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stop && S->queue.empty() && S->active.empty()) break;
+            while (!S->queue.empty() && (int)S->active.size() < S->max_active && !S->free_slots.empty()) {
+                ServedReq *r = S->queue.front();
+                if (S->used + r->foot > S->budget && !S->active.empty()) break;  // wait for memory
+                S->queue.pop_front();
+                S->used += r->foot;
+                r->slot = S->free_slots.back();
+                S->free_slots.pop_back();
+                r->state = 1;
+                S->active.push_back(r);
+                fresh.push_back(r);
+            }
+            S->max_in_flight = std::max<int64_t>(S->max_in_flight, (int64_t)S->active.size());
+            if (S->active.empty()) {
+                S->cv.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+        }
+        for (ServedReq *r : fresh) {
+            pp_status st = start_request(S, r);
+            if (st != PP_OK) {
+                (void)hipStreamSynchronize(S->main);
+                std::lock_guard<std::mutex> lk(S->mu);
+                complete(S, r, st);
+            }
+        }
+        // one iteration: the next pass of every active tiled request, one
+        // launch per tile size
+        std::vector<ServedReq *> tiled;
+        for (ServedReq *r : S->active)
+            if (r->state == 1 && r->prepared) tiled.push_back(r);
+        bool launched = false;
+        for (int k = 4; k <= 7 && !tiled.empty(); ++k) {
+            std::vector<ServedReq *> grp;
+            for (ServedReq *r : tiled)
+                if (r->c->dplan.k == k && r->pass < r->c->h_pass.size()) grp.push_back(r);
+            if (grp.empty()) continue;
+            std::stable_sort(grp.begin(), grp.end(), [](ServedReq *a, ServedReq *b) { return a->c->n > b->c->n; });
+            size_t i0 = 0;
+            while (i0 < grp.size()) {
+                std::vector<pp::TilePassDesc> td;
+                pp::TileGroups tg{};
+                int run = 0, last_n = -1;
+                size_t i = i0;
+                for (; i < grp.size(); ++i) {
+                    pp::TilePassDesc d = grp[i]->c->h_pass[grp[i]->pass];
+                    if (d.n != last_n) {
+                        if (tg.ngroups == pp::kMaxTileGroups) break;
+                        tg.first_block[tg.ngroups] = run;
+                        tg.first_desc[tg.ngroups] = (int32_t)td.size();
+                        tg.shift[tg.ngroups] = 2 * (d.n - k);
+                        tg.ngroups++;
+                        last_n = d.n;
+                    }
+                    d.tile_begin = run;
+                    run += d.ntiles;
+                    td.push_back(d);
+                }
+                tg.first_block[tg.ngroups] = run;
+                std::vector<unsigned char> blob(td.size() * sizeof(pp::TilePassDesc));
+                std::memcpy(blob.data(), td.data(), blob.size());
+                void *dd = nullptr;
+                pp_status st = ring_upload(S, blob, &dd);
+                if (st == PP_OK) {
+                    hipError_t e = pp::launch_tile_pass((const pp::TilePassDesc *)dd, tg, k, grp[i0]->c->dbytes,
+                                                        false, S->main);
+                    if (e != hipSuccess) st = fail(PP_ERR_DEVICE, hipGetErrorString(e));
+                }
+                ring_mark(S);
+                for (size_t j = i0; j < i; ++j) {
+                    ServedReq *r = grp[j];
+                    if (st != PP_OK) {
+                        std::lock_guard<std::mutex> lk(S->mu);
+                        complete(S, r, st);
+                        continue;
+                    }
+                    if (++r->pass == r->c->h_pass.size()) {
+                        pp_circuit *c = r->c;
+                        if (pp::launch_dense_readout(c->coef, c->n, c->dbytes, S->d_results + r->slot, S->main) !=
+                                hipSuccess ||
+                            finish_async(S, r, S->main) != PP_OK) {
+                            std::lock_guard<std::mutex> lk(S->mu);
+                            complete(S, r, PP_ERR_DEVICE);
+                        }
+                    }
+                }
+                S->tile_launches++;
+                launched = true;
+                i0 = i;
+            }
+        }
+        // tiled requests with no passes at all (empty circuits)
+        for (ServedReq *r : tiled)
+            if (r->state == 1 && r->c->h_pass.empty()) {
+                pp_circuit *c = r->c;
+                if (pp::launch_dense_readout(c->coef, c->n, c->dbytes, S->d_results + r->slot, S->main) != hipSuccess ||
+                    finish_async(S, r, S->main) != PP_OK) {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    complete(S, r, PP_ERR_DEVICE);
+                }
+            }
+        if (launched) S->iterations++;
+        // completions
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (ServedReq *r : S->active)
+                if (r->state == 2 && hipEventQuery(r->ev) == hipSuccess) complete(S, r, PP_OK);
+            bool any = false;
+            for (size_t i = 0; i < S->active.size();) {
+                ServedReq *r = S->active[i];
+                if (r->state == 3) {
+                    S->used -= r->foot;
+                    S->free_slots.push_back(r->slot);
+                    S->active[i] = S->active.back();
+                    S->active.pop_back();
+                    any = true;
+                } else {
+                    ++i;
+                }
+            }
+            if (any) S->done_cv.notify_all();
+        }
+        if (!launched) std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+}  // namespace
+
+extern "C" pp_status pp_server_create(int64_t mem_budget_bytes, int32_t max_active, pp_server **out) {
+    if (!out) return fail(PP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (mem_budget_bytes <= 0 || max_active <= 0 || max_active > 4096)
+        return fail(PP_ERR_INVALID, "budget must be > 0 and max_active in [1, 4096]");
+    pp_server *S = new (std::nothrow) pp_server();
+    if (!S) return fail(PP_ERR_NOMEM, "host allocation");
+    S->budget = mem_budget_bytes;
+    S->max_active = max_active;
+    hipError_t e = hipGetDevice(&S->dev);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->main, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void **)&S->d_results, sizeof(double) * max_active);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_results, sizeof(double) * max_active, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (S->main) (void)hipStreamDestroy(S->main);
+        if (S->side) (void)hipStreamDestroy(S->side);
+        if (S->d_results) (void)hipFree(S->d_results);
+        delete S;
+        return fail(PP_ERR_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
+    }
+    for (int i = max_active - 1; i >= 0; --i) S->free_slots.push_back(i);
+    S->th = std::thread(server_loop, S);
+    *out = S;
+    return PP_OK;
+}
+
+extern "C" pp_status pp_server_submit(pp_server *S, pp_circuit *c, int64_t *ticket) {
+    if (!S || !c || !ticket) return fail(PP_ERR_INVALID, "null argument");
+    pp_status r = check_ready(c);
+    if (r != PP_OK) return r;
+    ServedReq *q = new (std::nothrow) ServedReq();
+    if (!q) return fail(PP_ERR_NOMEM, "host allocation");
+    q->c = c;
+    q->foot = footprint_bytes(c);
+    if (q->foot > S->budget) {
+        delete q;
+        return fail(PP_ERR_CAPACITY, "request larger than the server memory budget");
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) {
+        delete q;
+        return fail(PP_ERR_STATE, "server is shutting down");
+    }
+    q->ticket = S->next_ticket++;
+    q->t_submit = now_s();
+    S->queue.push_back(q);
+    S->reqs[q->ticket] = q;
+    *ticket = q->ticket;
+    S->cv.notify_one();
+    return PP_OK;
+}
+
+extern "C" pp_status pp_server_poll(pp_server *S, int64_t ticket, int32_t *done, double *expval, double *latency_us) {
+    if (!S || !done) return fail(PP_ERR_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(PP_ERR_INVALID, "unknown ticket");
+    ServedReq *q = it->second;
+    *done = q->state == 3;
+    if (q->state == 3) {
+        if (expval) *expval = q->result;
+        if (latency_us) *latency_us = (q->t_done - q->t_submit) * 1e6;
+        if (q->status != PP_OK) return fail(q->status, "request failed");
+    }
+    return PP_OK;
+}
+
+extern "C" pp_status pp_server_drain(pp_server *S) {
+    if (!S) return fail(PP_ERR_INVALID, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->done_cv.wait(lk, [&] { return S->queue.empty() && S->active.empty(); });
+    return PP_OK;
+}
+
+extern "C" pp_status pp_server_counters(pp_server *S, int64_t *iterations, int64_t *tile_launches,
+                                        int64_t *max_in_flight) {
+    if (!S) return fail(PP_ERR_INVALID, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (iterations) *iterations = S->iterations;
+    if (tile_launches) *tile_launches = S->tile_launches;
+    if (max_in_flight) *max_in_flight = S->max_in_flight;
+    return PP_OK;
+}
+
+extern "C" void pp_server_destroy(pp_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    if (S->th.joinable()) S->th.join();
+    (void)hipStreamSynchronize(S->main);
+    (void)hipStreamSynchronize(S->side);
+    for (auto &kv : S->reqs) {
+        if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+        delete kv.second;
+    }
+    for (auto &R : S->ring) {
+        if (R.ev) (void)hipEventDestroy(R.ev);
+        if (R.d) (void)hipFree(R.d);
+        if (R.h) (void)hipHostFree(R.h);
+    }
+    (void)hipFree(S->d_results);
+    (void)hipHostFree(S->h_results);
+    (void)hipStreamDestroy(S->main);
+    (void)hipStreamDestroy(S->side);
+    delete S;
 }
