@@ -202,6 +202,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune", default="",
+                    help="tuning knobs, e.g. 'kernel:6=1,qubits:12=7' (tile kernel variant per k, tile qubits per n)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -223,6 +226,18 @@ def main():
 
     from paper_2502_10685_amd import _lib as L
     from paper_2502_10685_amd import api
+
+    for item in filter(None, args.tune.split(",")):
+        what, rest = item.split(":")
+        idx, val = rest.split("=")
+        L.tune_set(L.PP_TUNE_TILE_KERNEL if what == "kernel" else L.PP_TUNE_TILE_QUBITS, int(idx), int(val))
+
+    tuned = None
+    if not args.no_autotune and not args.tune and args.workload == "batch512":
+        from paper_2502_10685_amd import autotune
+        t0 = time.time()
+        tuned = autotune.tune(sizes=(8, 9, 10, 11, 12), dtype=args.dtype, save=False, log=log)
+        tuned["seconds"] = time.time() - t0
 
     circs, desc = build_workload(args.workload)
     log(f"workload {args.workload}: {len(circs)} circuits, {sum(w.m for w in circs)} gates")
@@ -279,6 +294,9 @@ def main():
            "step_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                "p99": float(np.percentile(lat, 99) * 1e3)},
            "kernels": kernels, "roofline": roof}
+    if tuned is not None:
+        res["autotune"] = {"tile_kernel": tuned["tile_kernel"], "tile_qubits": tuned["tile_qubits"],
+                           "seconds": round(tuned["seconds"], 1)}
 
     if not args.no_plain and len(objs) > 1:
         def plain():

@@ -217,6 +217,21 @@ PP_API pp_status pp_server_counters(pp_server *s, int64_t *iterations, int64_t *
  * NULL-safe. */
 PP_API void pp_server_destroy(pp_server *s);
 
+/* ------------------------------------------------------------ tuning */
+/* Library-wide tuning knobs (set by the autotuner, read when a schedule is
+ * built or a kernel launched):
+ *   PP_TUNE_TILE_QUBITS: index = n (8..16), value = default tile qubits k
+ *                        (4..7) for circuits without PP_OPT_TILE_QUBITS;
+ *   PP_TUNE_TILE_KERNEL: index = k (4..6), value = 0 one 256-thread
+ *                        workgroup per tile, 1 persistent 256-thread
+ *                        workgroups that prefetch the next tile, 2 one
+ *                        single-wave (64-thread) workgroup per tile.
+ * Both kernels give bit-identical results; k changes how ops are packed and
+ * therefore the rounding, so a circuit keeps the k of its schedule. */
+typedef enum pp_tune_key { PP_TUNE_TILE_QUBITS = 0, PP_TUNE_TILE_KERNEL = 1 } pp_tune_key;
+PP_API pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value);
+PP_API pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value);
+
 /* Host-only planning introspection (no device needed): runs the DENSE
  * scheduler on a gate list and reports the number of device ops and passes
  * for tiles of k qubits (k = n: one LDS-resident pass).  compose = fold a

@@ -13,6 +13,7 @@ STATUS_NAMES = ["PP_OK", "PP_ERR_INVALID", "PP_ERR_NOMEM", "PP_ERR_DEVICE", "PP_
 PP_F64, PP_F32 = 0, 1
 PP_ENGINE_AUTO, PP_ENGINE_DENSE, PP_ENGINE_SPARSE = 0, 1, 2
 PP_OPT_TRACK_TERMS, PP_OPT_TILE_QUBITS, PP_OPT_MAX_TERMS, PP_OPT_USE_GRAPH, PP_OPT_BLOCK = range(5)
+PP_TUNE_TILE_QUBITS, PP_TUNE_TILE_KERNEL = 0, 1
 
 
 class PPStats(ctypes.Structure):
@@ -73,6 +74,8 @@ def load():
         "pp_server_destroy": (None, [P]),
         "pp_plan_dense_info": (st, [I32, I64, P, P, P, P, I32, I32, I32, I32, ctypes.POINTER(I64),
                                     ctypes.POINTER(I64), P, I64]),
+        "pp_tune_set": (st, [ctypes.c_int, I32, I32]),
+        "pp_tune_get": (st, [ctypes.c_int, I32, ctypes.POINTER(I32)]),
         "pp_profile_enable": (st, [I32]),
         "pp_profile_read": (st, [ctypes.POINTER(PPKernelTime), I32, ctypes.POINTER(I32)]),
     }
@@ -120,3 +123,13 @@ def plan_dense_info(n, op, q0, q1, param, n_params, k, compose=True, reorder=Tru
     if want_passes:
         return nops.value, npass.value, buf[: npass.value].copy()
     return nops.value, npass.value
+
+
+def tune_set(key, index, value):
+    check(load().pp_tune_set(int(key), int(index), int(value)))
+
+
+def tune_get(key, index):
+    v = ctypes.c_int32(0)
+    check(load().pp_tune_get(int(key), int(index), ctypes.byref(v)))
+    return v.value

@@ -1,0 +1,131 @@
+"""Project autotuner: picks, by timing on the device, the tile-pass kernel
+variant per tile size and the tile size (qubits per LDS tile) per register
+size n, for batched throughput.  Results are cached as JSON keyed by the
+device name and weight dtype, and applied through pp_tune_set.
+
+Probes are seeded random circuits (50% H/S/CX, 50% RX/RY/RZ) evaluated in
+batches large enough to fill the GPU; every candidate gives bit-identical
+results for a fixed tile size, and a changed tile size only changes rounding
+(the schedule packs the same gates differently).
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+from . import _lib as L
+
+VARIANT_NAMES = {0: "workgroup-per-tile", 1: "persistent-prefetch", 2: "wave-per-tile"}
+
+
+def _device_name():
+    import torch
+    return torch.cuda.get_device_name(0).replace(" ", "_").replace("/", "_")
+
+
+def cache_path(dtype="f64"):
+    base = os.environ.get("PAULIPROP_TUNE_CACHE")
+    if base and base.endswith(".json"):
+        return base
+    d = base or os.path.join(os.path.expanduser("~"), ".cache", "pauliprop")
+    return os.path.join(d, f"tune_{_device_name()}_{dtype}.json")
+
+
+def apply(table):
+    for k, v in table.get("tile_kernel", {}).items():
+        L.tune_set(L.PP_TUNE_TILE_KERNEL, int(k), int(v))
+    for n, k in table.get("tile_qubits", {}).items():
+        L.tune_set(L.PP_TUNE_TILE_QUBITS, int(n), int(k))
+
+
+def load_cached(dtype="f64", apply_now=True):
+    p = cache_path(dtype)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        table = json.load(f)
+    if apply_now:
+        apply(table)
+    return table
+
+
+def _probe_batch(api, n, count, m, dtype, seed, tile_qubits=0):
+    from . import workloads as W
+    rng = np.random.default_rng(seed)
+    circs = []
+    for _ in range(count):
+        w = W.random_circuit(rng, n, m, W.obs_z(n, [0, 1]))
+        circs.append(api.Circuit.from_workload(w, dtype=dtype, engine="dense", tile_qubits=tile_qubits))
+    return circs
+
+
+def _time_batch(api, circs, reps=3):
+    import torch
+    out = torch.empty(len(circs), dtype=torch.float64, device="cuda")
+    api.evaluate_batch(circs, out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        api.evaluate_batch(circs, out)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def _count_for(n):
+    # enough tiles to fill 256 CUs several times over
+    return max(2, min(64, (1 << 16) // (4 ** (n - 6))))
+
+
+def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None):
+    """Times every candidate and returns (and applies, and caches) the table
+    {"tile_kernel": {k: variant}, "tile_qubits": {n: k}, "timings": ...}."""
+    from . import api
+    say = log or (lambda s: None)
+    table = {"tile_kernel": {}, "tile_qubits": {}, "timings": {"tile_kernel": {}, "tile_qubits": {}},
+             "device": _device_name(), "dtype": dtype, "probe_gates": m}
+    # 1. kernel variant per tile size k, on circuits with n = k + 3 tiled at k
+    for k in (4, 5, 6):
+        n = k + 3
+        circs = _probe_batch(api, n, _count_for(n), m, dtype, seed=9000 + k, tile_qubits=k)
+        best, times = None, {}
+        for v in (0, 1, 2):
+            L.tune_set(L.PP_TUNE_TILE_KERNEL, k, v)
+            times[v] = _time_batch(api, circs)
+            if best is None or times[v] < times[best]:
+                best = v
+        L.tune_set(L.PP_TUNE_TILE_KERNEL, k, best)
+        table["tile_kernel"][str(k)] = best
+        table["timings"]["tile_kernel"][str(k)] = {VARIANT_NAMES[v]: t for v, t in times.items()}
+        say(f"tile kernel k={k}: {VARIANT_NAMES[best]} ({ {VARIANT_NAMES[v]: round(t * 1e3, 2) for v, t in times.items()} } ms)")
+        for c in circs:
+            c.close()
+    # 2. tile size per n
+    for n in sizes:
+        best, times = None, {}
+        for k in (4, 5, 6, 7):
+            if k >= n:
+                continue
+            circs = _probe_batch(api, n, _count_for(n), m, dtype, seed=9100 + n, tile_qubits=k)
+            times[k] = _time_batch(api, circs)
+            for c in circs:
+                c.close()
+            if best is None or times[k] < times[best]:
+                best = k
+        if best is None:
+            continue
+        L.tune_set(L.PP_TUNE_TILE_QUBITS, n, best)
+        table["tile_qubits"][str(n)] = best
+        table["timings"]["tile_qubits"][str(n)] = {str(k): t for k, t in times.items()}
+        say(f"tile qubits n={n}: k={best} ({ {k: round(t * 1e3, 2) for k, t in times.items()} } ms)")
+    if save:
+        p = cache_path(dtype)
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        with open(p, "w") as f:
+            json.dump(table, f, indent=1)
+        table["cache"] = p
+    return table

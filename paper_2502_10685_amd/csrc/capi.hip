@@ -74,7 +74,8 @@ constexpr int kDenseMaxN = 16;
 constexpr int kAutoDenseMaxN = 13;
 constexpr int kLowQubits = 2;
 
-int default_tile_qubits(int n) { return n >= 10 ? 6 : 5; }
+int g_tile_qubits[17] = {0, 0, 0, 0, 0, 0, 0, 0, 5, 5, 6, 6, 6, 6, 6, 6, 6};
+int default_tile_qubits(int n) { return n >= 8 && n <= 16 ? g_tile_qubits[n] : (n > 16 ? 6 : 5); }
 
 // pinned staging for small asynchronous uploads, reused once the previous
 // upload from it has completed
@@ -616,10 +617,17 @@ pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *op, con
     }
     g.n_params = n_params;
     pp::DensePlan P = pp::plan_dense(g, k, kLowQubits, compose != 0, reorder != 0);
-    *n_ops = (int64_t)P.ops.size();
+    const std::string bad = pp::plan_check(P, n_qubits);
+    if (!bad.empty()) return fail(PP_ERR_STATE, "planner self-check: " + bad);
+    auto real_ops = [&](int b, int e) {
+        int cnt = 0;
+        for (int i = b; i < e; ++i) cnt += P.ops[i].kind != pp::DOP_GROUP;
+        return cnt;
+    };
+    *n_ops = real_ops(0, (int)P.ops.size());
     *n_passes = (int64_t)P.passes.size();
     for (int64_t i = 0; i < max_passes && i < (int64_t)P.passes.size(); ++i)
-        pass_ops[i] = P.passes[i].op_end - P.passes[i].op_begin;
+        pass_ops[i] = real_ops(P.passes[i].op_begin, P.passes[i].op_end);
     return PP_OK;
 }
 
@@ -1644,4 +1652,31 @@ extern "C" void pp_server_destroy(pp_server *S) {
     (void)hipStreamDestroy(S->main);
     (void)hipStreamDestroy(S->side);
     delete S;
+}
+
+extern "C" pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value) {
+    if (key == PP_TUNE_TILE_QUBITS) {
+        if (index < 8 || index > 16 || value < 4 || value > 7) return fail(PP_ERR_INVALID, "tile qubits: n in 8..16, k in 4..7");
+        g_tile_qubits[index] = value;
+        return PP_OK;
+    }
+    if (key == PP_TUNE_TILE_KERNEL) {
+        if (index < 4 || index > 6 || value < 0 || value > 2) return fail(PP_ERR_INVALID, "tile kernel: k in 4..6, value 0..2");
+        pp::set_tile_kernel_variant(index, value);
+        return PP_OK;
+    }
+    return fail(PP_ERR_INVALID, "unknown tuning key");
+}
+
+extern "C" pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value) {
+    if (!value) return fail(PP_ERR_INVALID, "null output");
+    if (key == PP_TUNE_TILE_QUBITS && index >= 8 && index <= 16) {
+        *value = g_tile_qubits[index];
+        return PP_OK;
+    }
+    if (key == PP_TUNE_TILE_KERNEL && index >= 4 && index <= 6) {
+        *value = pp::tile_kernel_variant(index);
+        return PP_OK;
+    }
+    return fail(PP_ERR_INVALID, "unknown tuning key or index");
 }

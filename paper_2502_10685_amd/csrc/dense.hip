@@ -20,6 +20,8 @@
 // it back, so HBM sees one read and one write per slot per pass however many
 // gates the pass holds.  Circuits with n <= 7 keep all 4^n slots in one
 // workgroup's LDS for the whole circuit.
+#include <algorithm>
+
 #include "pp_device.h"
 
 namespace pp {
@@ -30,6 +32,11 @@ namespace pp {
 // patterns used below (quads on digit 0, on digit 1, and on digits >= 2)
 // over distinct banks.
 __device__ __forceinline__ int sw(int i) { return i ^ (((i >> 4) & 3) * 5); }
+
+// For i = base | off with disjoint bits, sw(i) = sw(base) ^ sw(off): bits 4-5
+// of i are the disjoint union of those of base and off, and 5 * (p | q) =
+// 5p ^ 5q for disjoint two-bit p, q.  Slot offsets of an op's letters are
+// the same for every lane, so each address costs one XOR with a uniform.
 
 template <typename T>
 __device__ __forceinline__ double lds_ld(const T *p, int i) { return (double)p[sw(i)]; }
@@ -100,15 +107,16 @@ __device__ __forceinline__ int u1_apply(T *lc, uint8_t *lp, int a, const double 
     const double m10 = M[3], m11 = M[4], m12 = M[5];
     const double m20 = M[6], m21 = M[7], m22 = M[8];
     if (NQ < BLOCK && tid >= NQ) return 0;
+    const int oX = sw(1 << sh), oZ = sw(2 << sh), oY = sw(3 << sh);
     int iX[QPT], iY[QPT], iZ[QPT];
     double cx[QPT], cy[QPT], cz[QPT];
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
         const int u = tid + j * BLOCK;
-        const int base = ((u & ~lowmask) << 2) | (u & lowmask);
-        iX[j] = sw(base | (1 << sh));
-        iZ[j] = sw(base | (2 << sh));
-        iY[j] = sw(base | (3 << sh));
+        const int sbase = sw(((u & ~lowmask) << 2) | (u & lowmask));
+        iX[j] = sbase ^ oX;
+        iZ[j] = sbase ^ oZ;
+        iY[j] = sbase ^ oY;
         cx[j] = (double)lc[iX[j]];
         cy[j] = (double)lc[iY[j]];
         cz[j] = (double)lc[iZ[j]];
@@ -166,41 +174,142 @@ __device__ __forceinline__ CxPair cx_pair(int p) {
 template <typename T, bool TRACK, int K, int BLOCK>
 __device__ __forceinline__ void cx_apply(T *lc, uint8_t *lp, int a, int b, int tid) {
     constexpr int NG = 1 << (2 * (K - 2));
-    constexpr int NW = 6 * NG;
-    constexpr int WPT = (NW + BLOCK - 1) / BLOCK;
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     const int mlo = (1 << (2 * lo)) - 1, mhi = (1 << (2 * hi)) - 1;
     const int sa = 2 * a, sb = 2 * b;
-    int i1[WPT], i2[WPT];
-    bool neg[WPT], live[WPT];
-    double v1[WPT], v2[WPT];
+    if constexpr (NG >= BLOCK) {
+        // one thread per 16-slot group, all six swaps
+        int o1[6], o2[6];
 #pragma unroll
-    for (int j = 0; j < WPT; ++j) {
-        const int w = tid + j * BLOCK;
-        live[j] = (NW % BLOCK == 0) || w < NW;
-        const int u = w & (NG - 1);
-        const CxPair pr = cx_pair(w / NG);
-        int v = ((u & ~mlo) << 2) | (u & mlo);
-        v = ((v & ~mhi) << 2) | (v & mhi);
-        i1[j] = sw(v | (pr.dc1 << sa) | (pr.dt1 << sb));
-        i2[j] = sw(v | (pr.dc2 << sa) | (pr.dt2 << sb));
-        neg[j] = pr.neg;
-        if (live[j]) {
-            v1[j] = (double)lc[i1[j]];
-            v2[j] = (double)lc[i2[j]];
+        for (int p = 0; p < 6; ++p) {
+            const CxPair pr = cx_pair(p);
+            o1[p] = sw((pr.dc1 << sa) | (pr.dt1 << sb));
+            o2[p] = sw((pr.dc2 << sa) | (pr.dt2 << sb));
+        }
+#pragma unroll 1
+        for (int j = 0; j < NG / BLOCK; ++j) {
+            const int u = tid + j * BLOCK;
+            int v = ((u & ~mlo) << 2) | (u & mlo);
+            v = ((v & ~mhi) << 2) | (v & mhi);
+            const int sv = sw(v);
+            double v1[6], v2[6];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                v1[p] = (double)lc[sv ^ o1[p]];
+                v2[p] = (double)lc[sv ^ o2[p]];
+            }
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const bool neg = cx_pair(p).neg;
+                lc[sv ^ o1[p]] = (T)(neg ? -v2[p] : v2[p]);
+                lc[sv ^ o2[p]] = (T)(neg ? -v1[p] : v1[p]);
+                if (TRACK) {
+                    const uint8_t p1 = lp[sv ^ o1[p]], p2 = lp[sv ^ o2[p]];
+                    lp[sv ^ o1[p]] = p2;
+                    lp[sv ^ o2[p]] = p1;
+                }
+            }
+        }
+    } else {
+        // fewer groups than threads: work item w = pair * NG + group
+        constexpr int NW = 6 * NG;
+        constexpr int WPT = (NW + BLOCK - 1) / BLOCK;
+        int i1[WPT], i2[WPT];
+        bool neg[WPT], live[WPT];
+        double v1[WPT], v2[WPT];
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            const int w = tid + j * BLOCK;
+            live[j] = (NW % BLOCK == 0) || w < NW;
+            const int u = w & (NG - 1);
+            const CxPair pr = cx_pair(w / NG);
+            int v = ((u & ~mlo) << 2) | (u & mlo);
+            v = ((v & ~mhi) << 2) | (v & mhi);
+            const int sv = sw(v);
+            i1[j] = sv ^ sw((pr.dc1 << sa) | (pr.dt1 << sb));
+            i2[j] = sv ^ sw((pr.dc2 << sa) | (pr.dt2 << sb));
+            neg[j] = pr.neg;
+            if (live[j]) {
+                v1[j] = (double)lc[i1[j]];
+                v2[j] = (double)lc[i2[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            if (!live[j]) continue;
+            lc[i1[j]] = (T)(neg[j] ? -v2[j] : v2[j]);
+            lc[i2[j]] = (T)(neg[j] ? -v1[j] : v1[j]);
+            if (TRACK) {
+                const uint8_t p1 = lp[i1[j]], p2 = lp[i2[j]];
+                lp[i1[j]] = p2;
+                lp[i2[j]] = p1;
+            }
         }
     }
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) {
-        if (!live[j]) continue;
-        lc[i1[j]] = (T)(neg[j] ? -v2[j] : v2[j]);
-        lc[i2[j]] = (T)(neg[j] ? -v1[j] : v1[j]);
-        if (TRACK) {
-            const uint8_t p1 = lp[i1[j]], p2 = lp[i2[j]];
-            lp[i1[j]] = p2;
-            lp[i2[j]] = p1;
+}
+
+// The six signed swaps of CX as (control digit, target digit) pairs, derived
+// at compile time from the rule above; in the paper's letters they are
+// (I,Z)<->(Z,Z), (I,Y)<->(Z,Y), (X,I)<->(X,X), (X,Z)<->-(Y,Y), (X,Y)<->(Y,Z),
+// (Y,I)<->(Y,X) (digit values I=0 X=1 Z=2 Y=3).
+struct CxPairC { int dc1, dt1, dc2, dt2, neg; };
+constexpr CxPairC cx_pair_c(int p) {
+    int found = 0;
+    for (int dc = 0; dc < 4; ++dc)
+        for (int dt = 0; dt < 4; ++dt) {
+            const int xc = dc & 1, zc = dc >> 1, xt = dt & 1, zt = dt >> 1;
+            const int dc2 = xc | ((zc ^ zt) << 1), dt2 = (xt ^ xc) | (zt << 1);
+            if (dc2 * 4 + dt2 > dc * 4 + dt) {
+                if (found == p) return CxPairC{dc, dt, dc2, dt2, xc & zt & ((xt ^ zc) ^ 1)};
+                ++found;
+            }
         }
-    }
+    return CxPairC{0, 0, 0, 0, 0};
+}
+static_assert(cx_pair_c(3).dc1 == 1 && cx_pair_c(3).dt1 == 2 && cx_pair_c(3).dc2 == 3 && cx_pair_c(3).dt2 == 3 &&
+                  cx_pair_c(3).neg == 1,
+              "XZ <-> -YY");
+
+template <bool CTRL_LO, int P>
+__device__ __forceinline__ void cx_swap(double *v) {
+    constexpr CxPairC pr = cx_pair_c(P);
+    constexpr int e1 = CTRL_LO ? pr.dc1 + 4 * pr.dt1 : pr.dt1 + 4 * pr.dc1;
+    constexpr int e2 = CTRL_LO ? pr.dc2 + 4 * pr.dt2 : pr.dt2 + 4 * pr.dc2;
+    const double t1 = v[e1], t2 = v[e2];
+    v[e1] = pr.neg ? -t2 : t2;
+    v[e2] = pr.neg ? -t1 : t1;
+}
+
+// CX on a 16-register block v[dlo + 4 * dhi] of two digits; CTRL_LO: the
+// control is the lower digit of the pair.
+template <bool CTRL_LO>
+__device__ __forceinline__ void cx_regs(double *v) {
+    cx_swap<CTRL_LO, 0>(v);
+    cx_swap<CTRL_LO, 1>(v);
+    cx_swap<CTRL_LO, 2>(v);
+    cx_swap<CTRL_LO, 3>(v);
+    cx_swap<CTRL_LO, 4>(v);
+    cx_swap<CTRL_LO, 5>(v);
+}
+
+template <bool LO, int Q>
+__device__ __forceinline__ void u1_quad(double *v, const double (&m)[9]) {
+    constexpr int iX = LO ? 1 + 4 * Q : Q + 4, iZ = LO ? 2 + 4 * Q : Q + 8, iY = LO ? 3 + 4 * Q : Q + 12;
+    const double cx = v[iX], cy = v[iY], cz = v[iZ];
+    v[iX] = m[0] * cx + m[1] * cy + m[2] * cz;
+    v[iY] = m[3] * cx + m[4] * cy + m[5] * cz;
+    v[iZ] = m[6] * cx + m[7] * cy + m[8] * cz;
+}
+
+// U1 (3x3 map M over X, Y, Z) on one digit of a 16-register block; LO: the
+// lower digit of the pair.
+template <bool LO>
+__device__ __forceinline__ void u1_regs(double *v, const double *M) {
+    const double m[9] = {M[0], M[1], M[2], M[3], M[4], M[5], M[6], M[7], M[8]};
+    u1_quad<LO, 0>(v, m);
+    u1_quad<LO, 1>(v, m);
+    u1_quad<LO, 2>(v, m);
+    u1_quad<LO, 3>(v, m);
 }
 
 // Ops and their maps are staged through LDS in chunks: one cooperative load
@@ -211,17 +320,54 @@ struct OpCache {
     double maps[OPCH][9];
 };
 
+// A GROUP of cnt ops on digits a < b: each thread owns whole 16-slot blocks
+// (all letters of the two digits), applies every member op in registers and
+// writes the block back once.
+template <typename T, int K, int BLOCK>
+__device__ __forceinline__ void group_apply(T *lc, int a, int b, const OpCache *oc, int first, int cnt, int tid) {
+    constexpr int NG = 1 << (2 * (K - 2));
+    constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
+    if (NG < BLOCK && tid >= NG) return;
+    const int mlo = (1 << (2 * a)) - 1, mhi = (1 << (2 * b)) - 1;
+#pragma unroll 1
+    for (int j = 0; j < GPT; ++j) {
+        const int u = tid + j * BLOCK;
+        int v0 = ((u & ~mlo) << 2) | (u & mlo);
+        v0 = ((v0 & ~mhi) << 2) | (v0 & mhi);
+        const int sv = sw(v0);
+        double v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * a)) | ((e >> 2) << (2 * b)))];
+#pragma unroll 1
+        for (int t = first; t < first + cnt; ++t) {
+            const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[t])[0]);
+            const int kind = w0 & 0xff, da = (w0 >> 8) & 0xff;
+            if (kind == DOP_U1) {
+                if (da == a) u1_regs<true>(v, oc->maps[t]);
+                else u1_regs<false>(v, oc->maps[t]);
+            } else {
+                if (da == a) cx_regs<true>(v);
+                else cx_regs<false>(v);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lc[sv ^ sw(((e & 3) << (2 * a)) | ((e >> 2) << (2 * b)))] = (T)v[e];
+    }
+}
+
 // Applies ops [o0, o1) to an LDS tile of 4^K slots.  For tracked runs it
 // accumulates term updates: every op adds ngates * (strings in the tile
 // before it), and U1 ops that can create strings update that count.
 template <typename T, bool TRACK, int K, int BLOCK>
-__device__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const double *__restrict__ maps, int o0,
-                        int o1, long long &tcount, long long &updates, long long *redi, OpCache *oc) {
+__device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const double *__restrict__ maps, int o0,
+                        int o1, long long &tcount, long long &updates, long long *redi, OpCache *oc,
+                        bool preloaded = false) {
     const int tid = threadIdx.x;
-    for (int cb = o0; cb < o1; cb += OPCH) {
+    int cb = o0;
+    while (cb < o1) {
         const int cn = (o1 - cb) < OPCH ? (o1 - cb) : OPCH;
         __syncthreads();
-        if (tid < cn) {
+        if (!preloaded && tid < cn) {
             const DOp op = ops[cb + tid];
             oc->ops[tid] = op;
             if (op.kind == DOP_U1) {
@@ -231,24 +377,33 @@ __device__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const d
             }
         }
         __syncthreads();
-        for (int i = 0; i < cn; ++i) {
+        preloaded = false;
+        int i = 0;
+        while (i < cn) {
             // op fields are the same for every lane: keep them in SGPRs
             const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[0]);
             const uint32_t w1 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[1]);
             const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, b = (w0 >> 16) & 0xff, ngates = (w0 >> 24) & 0xff;
             const unsigned smask = w1 & 0xffff, perm = w1 >> 16;
-            if (kind == DOP_U1) {
+            if (kind == DOP_GROUP) {
+                if (i + 1 + ngates > cn) break;  // reload the chunk from this header
+                if constexpr (K >= 2) group_apply<T, K, BLOCK>(lc, a, b, oc, i + 1, ngates, tid);
+                i += 1 + ngates;
+            } else if (kind == DOP_U1) {
                 const int delta = u1_apply<T, TRACK, K, BLOCK>(lc, lp, a, oc->maps[i], smask, tid);
                 if (TRACK) {
                     updates += tcount * ngates;
                     if (!perm) tcount += block_sum_i<BLOCK>(delta, redi);
                 }
+                ++i;
             } else {
                 if constexpr (K >= 2) cx_apply<T, TRACK, K, BLOCK>(lc, lp, a, b, tid);
                 if (TRACK) updates += tcount * ngates;
+                ++i;
             }
             __syncthreads();
         }
+        cb += i;
     }
 }
 
@@ -257,7 +412,7 @@ __device__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const d
 // observable, applies every op, reads out <O> and optionally stores the
 // final weights / presence for pp_get_terms.
 template <typename T, bool TRACK, int N, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void resident_kernel(const ResidentDesc *__restrict__ descs) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK >= 512 ? 2 : 4))) void resident_kernel(const ResidentDesc *__restrict__ descs) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double redd[BLOCK / 64];
     __shared__ long long redi[BLOCK / 64];
@@ -319,7 +474,7 @@ __global__ __launch_bounds__(BLOCK) void resident_kernel(const ResidentDesc *__r
 // digit j is global qubit qubit[j] (ascending), so the leading local digits
 // that equal their qubit form contiguous runs in HBM.
 template <typename T, bool TRACK, int K, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void tile_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((BLOCK == 64 && K >= 6) ? 1 : (K >= 7 ? 2 : 4)))) void tile_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long redi[BLOCK / 64];
     __shared__ OpCache oc;
@@ -349,14 +504,15 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(const TilePassDesc *__restr
             t >>= 2;
         }
     }
-    // local index i = tid + r * BLOCK; BLOCK = 4^4, so the thread supplies
-    // digits 0-3 and r the digits above
-    static_assert(BLOCK == 256, "tile kernel assumes 256 threads");
-    const long long toff = base | deposit_digits(tid, d.qubits, 0, k < 4 ? k : 4);
+    // local index i = tid + r * BLOCK with BLOCK a power of two: tid and
+    // r * BLOCK have disjoint bits, so their digit deposits simply OR, and
+    // the r part is the same for every lane
+    static_assert((BLOCK & (BLOCK - 1)) == 0 && BLOCK <= size, "a tile holds at least one slot per thread");
+    const long long toff = base | deposit_digits(tid, d.qubits, 0, k);
 
     T *g = reinterpret_cast<T *>(d.coef);
     for (int i = tid, r = 0; i < size; i += BLOCK, ++r) {
-        const long long gi = toff | deposit_digits(r << 8, d.qubits, 4, k);
+        const long long gi = toff | deposit_digits(r * BLOCK, d.qubits, 0, k);
         lc[sw(i)] = g[gi];
         if (TRACK) lp[sw(i)] = d.pres[gi];
     }
@@ -371,11 +527,115 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(const TilePassDesc *__restr
     run_ops<T, TRACK, K, BLOCK>(lc, lp, d.ops, d.maps, d.op_begin, d.op_end, tcount, updates, redi, &oc);
 
     for (int i = tid, r = 0; i < size; i += BLOCK, ++r) {
-        const long long gi = toff | deposit_digits(r << 8, d.qubits, 4, k);
+        const long long gi = toff | deposit_digits(r * BLOCK, d.qubits, 0, k);
         g[gi] = lc[sw(i)];
         if (TRACK) d.pres[gi] = lp[sw(i)];
     }
     if (TRACK && tid == 0 && updates) atomicAdd(d.counters, (unsigned long long)updates);
+}
+
+// ------------------------------------------------- streaming tile kernel
+// Persistent form of tile_kernel for untracked runs: a co-resident grid
+// walks the launch's tiles with stride gridDim.x, and every workgroup issues
+// the global loads of its next tile into registers before it runs the ops of
+// the current one, so HBM latency overlaps the LDS work.
+struct TileLoc {
+    const TilePassDesc *d;
+    long long toff;
+};
+
+template <int K>
+__device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ descs, const TileGroups &grp, int b,
+                                               int tid) {
+    int g = 0;
+    while (g + 1 < grp.ngroups && b >= grp.first_block[g + 1]) ++g;
+    const int rel = b - grp.first_block[g];
+    const TilePassDesc *d = descs + grp.first_desc[g] + (rel >> grp.shift[g]);
+    const long long tile = rel & ((1 << grp.shift[g]) - 1);
+    const uint64_t qubits = d->qubits;
+    const int n = d->n;
+    unsigned inmask = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < K) inmask |= 1u << (unsigned)((qubits >> (8 * j)) & 0xff);
+    long long base = 0, t = tile;
+    for (int q = 0; q < n; ++q) {
+        if ((inmask >> q) & 1u) continue;
+        base |= (t & 3ll) << (2 * q);
+        t >>= 2;
+    }
+    return TileLoc{d, base | deposit_digits(tid, qubits, 0, 4)};
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void tile_stream_kernel(
+    const TilePassDesc *__restrict__ descs, TileGroups grp) {
+    constexpr int BLOCK = 256;
+    constexpr int size = 1 << (2 * K);
+    constexpr int PER = size / BLOCK;
+    static_assert(K >= 4, "the thread index supplies four digits");
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long redi[BLOCK / 64];
+    __shared__ OpCache oc;
+    T *lc = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x;
+    const int total = grp.first_block[grp.ngroups];
+    int blk = blockIdx.x;
+    if (blk >= total) return;
+    TileLoc cur = locate_tile<K>(descs, grp, blk, tid);
+    T pre[PER];
+    {
+        const T *g = reinterpret_cast<const T *>(cur.d->coef);
+        const uint64_t qubits = cur.d->qubits;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) pre[r] = g[cur.toff | deposit_digits(r << 8, qubits, 4, K)];
+    }
+    long long tcount = 0, updates = 0;
+    for (;;) {
+        __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int r = 0; r < PER; ++r) lc[sw(tid + r * BLOCK)] = pre[r];
+        const int o0 = cur.d->op_begin, o1 = cur.d->op_end;
+        const int cn = (o1 - o0) < OPCH ? (o1 - o0) : OPCH;
+        // first op chunk of this tile, then the next tile's prefetch
+        DOp opr{};
+        double mr[9];
+        if (tid < cn) {
+            opr = cur.d->ops[o0 + tid];
+            if (opr.kind == DOP_U1) {
+                const double *src = cur.d->maps + 9ull * opr.map;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) mr[j] = src[j];
+            }
+        }
+        const int nblk = blk + gridDim.x;
+        const bool has_next = nblk < total;
+        TileLoc nxt = cur;
+        if (has_next) {
+            nxt = locate_tile<K>(descs, grp, nblk, tid);
+            const T *g = reinterpret_cast<const T *>(nxt.d->coef);
+            const uint64_t qubits = nxt.d->qubits;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) pre[r] = g[nxt.toff | deposit_digits(r << 8, qubits, 4, K)];
+        }
+        if (tid < cn) {
+            oc.ops[tid] = opr;
+            if (opr.kind == DOP_U1) {
+#pragma unroll
+                for (int j = 0; j < 9; ++j) oc.maps[tid][j] = mr[j];
+            }
+        }
+        run_ops<T, false, K, BLOCK>(lc, nullptr, cur.d->ops, cur.d->maps, o0, o1, tcount, updates, redi, &oc, true);
+        {
+            T *g = reinterpret_cast<T *>(cur.d->coef);
+            const uint64_t qubits = cur.d->qubits;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) g[cur.toff | deposit_digits(r << 8, qubits, 4, K)] = lc[sw(tid + r * BLOCK)];
+        }
+        if (!has_next) break;
+        blk = nblk;
+        cur = nxt;
+    }
 }
 
 // ------------------------------------------------------ adjoint sweep
@@ -706,9 +966,54 @@ hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int d
                  : launch_res_b<float, false>(d_descs, ndescs, n, lds, s);
 }
 
+static int g_tile_variant[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+void set_tile_kernel_variant(int k, int variant) {
+    if (k >= 0 && k < 8) g_tile_variant[k] = variant;
+}
+int tile_kernel_variant(int k) { return (k >= 0 && k < 8) ? g_tile_variant[k] : 0; }
+
+int num_cus() {
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        cached = v;
+    return cached > 0 ? cached : 256;
+}
+
 template <typename T, bool TRACK, int K>
 static hipError_t launch_tile_t(const TilePassDesc *d, const TileGroups &grp, size_t lds, hipStream_t s) {
-    auto fn = tile_kernel<T, TRACK, K, 256>;
+    const int nblocks = grp.first_block[grp.ngroups];
+    if (!TRACK && K <= 6 && g_tile_variant[K] == 2) {
+        auto fn = tile_kernel<T, false, (K <= 6 ? K : 6), 64>;
+        static bool attr64 = false;
+        if (!attr64) {
+            hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               max_lds_bytes() - (int)kStaticLdsReserve);
+            if (e != hipSuccess) return e;
+            attr64 = true;
+        }
+        hipLaunchKernelGGL(fn, dim3(nblocks), dim3(64), lds, s, d, grp);
+        return hipGetLastError();
+    }
+    if (!TRACK && K <= 6 && g_tile_variant[K] == 1) {
+        auto fn = tile_stream_kernel<T, (K <= 6 ? K : 6)>;
+        static int resident_blocks = 0;
+        if (!resident_blocks) {
+            hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               max_lds_bytes() - (int)kStaticLdsReserve);
+            if (e != hipSuccess) return e;
+            int per_cu = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256, lds);
+            if (e != hipSuccess) return e;
+            resident_blocks = std::max(per_cu, 1) * num_cus();
+        }
+        const int grid = nblocks < resident_blocks ? nblocks : resident_blocks;
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, s, d, grp);
+        return hipGetLastError();
+    }
+    constexpr int TB = K >= 7 ? 512 : 256;
+    auto fn = tile_kernel<T, TRACK, K, TB>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -716,8 +1021,7 @@ static hipError_t launch_tile_t(const TilePassDesc *d, const TileGroups &grp, si
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int nblocks = grp.first_block[grp.ngroups];
-    hipLaunchKernelGGL(fn, dim3(nblocks), dim3(256), lds, s, d, grp);
+    hipLaunchKernelGGL(fn, dim3(nblocks), dim3(TB), lds, s, d, grp);
     return hipGetLastError();
 }
 

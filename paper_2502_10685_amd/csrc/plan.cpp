@@ -50,11 +50,89 @@ unsigned smask_compose(unsigned after, unsigned before) {
 DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder) {
     PlanOptions o;
     o.compose = compose;
+    o.group = compose;
     o.reorder = reorder;
     return plan_dense_opts(g, k, low, o);
 }
 
+namespace {
+
+unsigned op_digits(const DOp &d) { return d.kind == DOP_CX ? (1u << d.a) | (1u << d.b) : (1u << d.a); }
+
+// Regroups ops [b, e) of P.ops: repeatedly takes the first remaining op and
+// every later op whose digits stay within one pair of digits and that does
+// not share a digit with an op it would move past (ops on disjoint digits
+// commute).  Groups of two or more ops get a GROUP header.
+void group_pass(DensePlan &P, int b, int e, int k) {
+    std::vector<DOp> in(P.ops.begin() + b, P.ops.begin() + e), out;
+    std::vector<char> used(in.size(), 0);
+    for (size_t i = 0; i < in.size(); ++i) {
+        if (used[i]) continue;
+        unsigned pair = op_digits(in[i]), skipped = 0;
+        std::vector<size_t> mem{i};
+        used[i] = 1;
+        for (size_t j = i + 1; j < in.size() && (int)mem.size() < kMaxGroupOps; ++j) {
+            if (used[j]) continue;
+            const unsigned d = op_digits(in[j]);
+            if (d & skipped) {
+                skipped |= d;
+                continue;
+            }
+            if (__builtin_popcount(pair | d) <= 2) {
+                pair |= d;
+                mem.push_back(j);
+                used[j] = 1;
+            } else {
+                skipped |= d;
+            }
+        }
+        if (mem.size() > 1 && __builtin_popcount(pair) == 1) {
+            if (k < 2) {  // a one-digit tile has no pair: keep the ops as they are
+                for (size_t j : mem) out.push_back(in[j]);
+                continue;
+            }
+            pair |= 1u << (pair == 1u ? 1 : 0);  // any second digit completes the block
+        }
+        if (mem.size() == 1) {
+            out.push_back(in[i]);
+            continue;
+        }
+        DOp h{};
+        h.kind = DOP_GROUP;
+        h.a = (uint8_t)__builtin_ctz(pair);
+        h.b = (uint8_t)(31 - __builtin_clz(pair));
+        h.ngates = (uint8_t)mem.size();
+        out.push_back(h);
+        for (size_t j : mem) out.push_back(in[j]);
+    }
+    P.ops.erase(P.ops.begin() + b, P.ops.begin() + e);
+    P.ops.insert(P.ops.begin() + b, out.begin(), out.end());
+}
+
+void group_all(DensePlan &P) {
+    int shift = 0;
+    for (DensePass &ps : P.passes) {
+        ps.op_begin += shift;
+        ps.op_end += shift;
+        const int before = (int)P.ops.size();
+        group_pass(P, ps.op_begin, ps.op_end, ps.k);
+        const int added = (int)P.ops.size() - before;
+        ps.op_end += added;
+        shift += added;
+    }
+}
+
+}  // namespace
+
+static DensePlan plan_dense_core(const GateList &g, int k, int low, const PlanOptions &o);
+
 DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &o) {
+    DensePlan P = plan_dense_core(g, k, low, o);
+    if (o.group && o.compose && !o.slot) group_all(P);
+    return P;
+}
+
+static DensePlan plan_dense_core(const GateList &g, int k, int low, const PlanOptions &o) {
     DensePlan P;
     const int n = g.n;
     const bool compose = o.compose, reorder = o.reorder;
@@ -75,7 +153,7 @@ DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &
     if (P.resident) {
         DensePass pass;
         pass.k = n;
-        for (int j = 0; j < n; ++j) pass.qubit[j] = (uint8_t)j;
+        for (int j = 0; j < n && j < 8; ++j) pass.qubit[j] = (uint8_t)j;
         // Composition needs each map's recipe to be contiguous; gates on
         // other wires in between would interleave recipes.  Collect, per op,
         // its gates first, then emit recipes in op order.
@@ -266,6 +344,39 @@ DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &
         P.passes.push_back(pass);
     }
     return P;
+}
+
+std::string plan_check(const DensePlan &P, int n) {
+    int expect = 0;
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const DensePass &ps = P.passes[p];
+        if (ps.op_begin != expect || ps.op_end < ps.op_begin) return "passes do not tile the op list";
+        expect = ps.op_end;
+        const int k = ps.k;
+        if (k < 1 || k > n || (k < n && k > 8)) return "bad tile size";
+        for (int j = 1; j < k && j < 8; ++j)
+            if (ps.qubit[j] <= ps.qubit[j - 1] || ps.qubit[j] >= n) return "tile qubits not ascending";
+        for (int i = ps.op_begin; i < ps.op_end; ++i) {
+            const DOp &d = P.ops[i];
+            if (d.kind == DOP_GROUP) {
+                if (d.a == d.b || d.a >= k || d.b >= k || d.ngates < 2 || i + d.ngates >= ps.op_end)
+                    return "bad GROUP header";
+                for (int j = i + 1; j <= i + d.ngates; ++j) {
+                    const DOp &m = P.ops[j];
+                    if (m.kind == DOP_GROUP) return "nested GROUP";
+                    if (m.a != d.a && m.a != d.b) return "GROUP member outside its pair";
+                    if (m.kind == DOP_CX && ((m.b != d.a && m.b != d.b) || m.a == m.b)) return "GROUP CX outside its pair";
+                    if (m.kind == DOP_U1 && m.map >= (uint32_t)P.nmaps()) return "map index out of range";
+                }
+                i += d.ngates;
+                continue;
+            }
+            if (d.a >= k || (d.kind == DOP_CX && (d.b >= k || d.a == d.b))) return "op digit outside the tile";
+            if (d.kind == DOP_U1 && d.map >= (uint32_t)P.nmaps()) return "map index out of range";
+        }
+    }
+    if (expect != (int)P.ops.size()) return "ops outside every pass";
+    return "";
 }
 
 void plan_append(DensePlan &all, const DensePlan &part) {

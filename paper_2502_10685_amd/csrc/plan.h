@@ -3,6 +3,7 @@
 
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "pp_device.h"
@@ -50,6 +51,7 @@ struct SparsePlan {
 // k == n: one resident pass; k < n: passes of k-qubit tiles that always
 // contain the lowest `low` qubits.
 DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder);
+constexpr int kMaxGroupOps = 16;
 
 // General form: gates [g_begin, g_end) only; forward = g_begin first (the
 // adjoint sweep) instead of Heisenberg order; slot (optional, size m): for
@@ -57,12 +59,19 @@ DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reord
 // to the rotation's op code.
 struct PlanOptions {
     bool compose = true;
+    bool group = true;  // pack ops on a common digit pair into GROUP ops
     bool reorder = true;
     bool forward = false;
     int64_t g_begin = 0, g_end = -1;
     const std::vector<int32_t> *slot = nullptr;
 };
 DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &o);
+
+// Structural checks of a dense schedule (used by the host-side tests):
+// GROUP headers name two distinct digits below k and their members act only
+// on them, passes tile the op list, digits are below the tile size, map
+// indices are in range.  Returns an empty string or the first violation.
+std::string plan_check(const DensePlan &P, int n);
 
 // Appends `part` to `all`, offsetting op, map and recipe indices.
 void plan_append(DensePlan &all, const DensePlan &part);

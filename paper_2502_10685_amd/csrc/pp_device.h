@@ -13,11 +13,13 @@ namespace pp {
 // i.e. qubit q owns the base-4 digit q (digit value x + 2z: I=0 X=1 Z=2 Y=3).
 // This is the paper's index space 0 ... 4^n - 1 (Sec. III-B) with a digit
 // order that makes a qubit's four letters one digit of the slot index.
-enum : uint8_t { DOP_U1 = 0, DOP_CX = 1 };
+enum : uint8_t { DOP_U1 = 0, DOP_CX = 1, DOP_GROUP = 2 };
 
 // One device operation on an LDS tile.  U1: a composed single-qubit map on
 // local digit a (a real 3x3 matrix over the X, Y, Z weights, I is fixed).
-// CX: control digit a, target digit b.  16 bytes, read uniformly.
+// CX: control digit a, target digit b.  GROUP: header of the next ngates ops,
+// which act only on digits a and b; a thread applies all of them to each
+// 16-slot block of those two digits in registers.  16 bytes, read uniformly.
 struct DOp {
     uint8_t kind;
     uint8_t a, b;
@@ -120,6 +122,9 @@ hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int d
                            hipStream_t s);
 hipError_t launch_tile_pass(const TilePassDesc *d_descs, const TileGroups &groups, int k, int dtype_bytes,
                             bool track, hipStream_t s);
+// 0: one workgroup per tile; 1: persistent prefetching workgroups (k <= 6)
+void set_tile_kernel_variant(int k, int variant);
+int tile_kernel_variant(int k);
 hipError_t launch_grad_pass(const GradPassDesc *d_desc, int ntiles, int k, hipStream_t s);
 hipError_t launch_grad_init_state(double *r, int n, hipStream_t s);
 hipError_t launch_grad_reduce(const double *partials, int nslots, int ntiles, double *rot_grad, hipStream_t s);

@@ -79,3 +79,22 @@ def test_planner_host_logic():
         L.plan_dense_info(9, w.op, w.q0 + 20, w.q1, w.param, w.n_params, 5)
     with pytest.raises(L.PauliPropError):
         L.plan_dense_info(9, w.op, w.q0, w.q1, w.param, w.n_params, 3)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpauliprop.so not built")
+@pytest.mark.parametrize("n", list(range(1, 13)))
+def test_planner_self_check_random(n):
+    """The planner's structural self-check holds for random circuits of every
+    size, for LDS-resident schedules and every tile size."""
+    import numpy as np
+    from paper_2502_10685_amd import _lib as L
+    from paper_2502_10685_amd import workloads as W
+    rng = np.random.default_rng(700 + n)
+    for rep in range(3):
+        w = W.random_circuit(rng, n, int(rng.integers(1, 1500)))
+        ks = [n] + [k for k in (4, 5, 6, 7) if k < n]
+        for k in ks:
+            for compose in (True, False):
+                ops, passes = L.plan_dense_info(n, w.op, w.q0, w.q1, w.param, w.n_params, k, compose=compose,
+                                                reorder=compose)
+                assert ops >= 1 and passes >= 1

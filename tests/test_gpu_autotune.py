@@ -1,0 +1,40 @@
+"""Autotuner: it times the candidates on the device, applies the winners
+through the library's tuning knobs, caches them, and results stay correct."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_10685_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_applies_and_caches(tmp_path, monkeypatch):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2502_10685_amd import _lib as L
+    from paper_2502_10685_amd import api, autotune
+    monkeypatch.setenv("PAULIPROP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    saved = {k: L.tune_get(L.PP_TUNE_TILE_KERNEL, k) for k in (4, 5, 6)}
+    saved_q = {n: L.tune_get(L.PP_TUNE_TILE_QUBITS, n) for n in (8, 9)}
+    try:
+        table = autotune.tune(sizes=(8, 9), m=150)
+        for k, v in table["tile_kernel"].items():
+            assert L.tune_get(L.PP_TUNE_TILE_KERNEL, int(k)) == v
+        for n, k in table["tile_qubits"].items():
+            assert L.tune_get(L.PP_TUNE_TILE_QUBITS, int(n)) == k
+        with open(tmp_path / "tune.json") as f:
+            assert json.load(f)["tile_qubits"] == table["tile_qubits"]
+        rng = np.random.default_rng(77)
+        wc = W.random_circuit(rng, 9, 300, W.obs_z(9, [0, 2]))
+        c = api.Circuit.from_workload(wc)
+        assert abs(float(c.evaluate().item()) - oracle.expval_sv(wc)) <= 1e-12
+        assert c.stats()["tile_qubits"] == table["tile_qubits"]["9"]
+    finally:
+        for k, v in saved.items():
+            L.tune_set(L.PP_TUNE_TILE_KERNEL, k, v)
+        for n, k in saved_q.items():
+            L.tune_set(L.PP_TUNE_TILE_QUBITS, n, k)

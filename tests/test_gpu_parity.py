@@ -299,3 +299,27 @@ def test_invalid_inputs(api):
     c = api.Circuit(wc.n, wc.op, wc.q0, wc.q1, wc.param, wc.n_params, wc.obs_x, wc.obs_z, wc.obs_c)
     with pytest.raises(PauliPropError):
         c.evaluate()  # theta never set
+
+
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_tile_kernel_variants_bitwise(api, k):
+    """The three tile-pass kernels (one 256-thread workgroup per tile,
+    persistent prefetching workgroups, one wave per tile) run the same ops in
+    the same order on every tile, so results are identical bit for bit."""
+    from paper_2502_10685_amd import _lib as L
+    rng = np.random.default_rng(600 + k)
+    n = k + 3
+    wc = W.random_circuit(rng, n, 900, W.obs_tfim(n))
+    sv = oracle.expval_sv(wc)
+    vals = []
+    old = L.tune_get(L.PP_TUNE_TILE_KERNEL, k)
+    try:
+        for variant in (0, 1, 2):
+            L.tune_set(L.PP_TUNE_TILE_KERNEL, k, variant)
+            c = api.Circuit.from_workload(wc, engine="dense", tile_qubits=k)
+            vals.append(float(c.evaluate().item()))
+            c.close()
+    finally:
+        L.tune_set(L.PP_TUNE_TILE_KERNEL, k, old)
+    assert vals[0] == vals[1] == vals[2], vals
+    assert abs(vals[0] - sv) <= TOL64
