@@ -45,7 +45,7 @@ def build_workload(name):
     elif name == "hea8":
         circs = [W.config4()]
         desc = "n=8, HEA 40 layers (1,280 gates, 960 params), O=TFIM (15 terms), seed 4"
-    elif name in ("rand10", "rand12"):
+    elif name in ("rand7", "rand10", "rand12"):
         n = int(name[4:])
         circs = [W.random_circuit(10 + n, n, 6000, W.obs_z(n, [0, 1]))]
         desc = f"n={n}, 6,000 random gates (50% Clifford), O=Z0Z1, seed {10 + n}"
@@ -202,7 +202,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the tuning candidates on this device first (defaults are MI355X measurements)")
     ap.add_argument("--tune", default="",
                     help="tuning knobs, e.g. 'kernel:6=1,qubits:12=7' (tile kernel variant per k, tile qubits per n)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -230,10 +231,11 @@ def main():
     for item in filter(None, args.tune.split(",")):
         what, rest = item.split(":")
         idx, val = rest.split("=")
-        L.tune_set(L.PP_TUNE_TILE_KERNEL if what == "kernel" else L.PP_TUNE_TILE_QUBITS, int(idx), int(val))
+        key = {"kernel": L.PP_TUNE_TILE_KERNEL, "qubits": L.PP_TUNE_TILE_QUBITS, "resblock": L.PP_TUNE_RESIDENT_BLOCK}
+        L.tune_set(key[what], int(idx), int(val))
 
     tuned = None
-    if not args.no_autotune and not args.tune and args.workload == "batch512":
+    if args.autotune:
         from paper_2502_10685_amd import autotune
         t0 = time.time()
         tuned = autotune.tune(sizes=(8, 9, 10, 11, 12), dtype=args.dtype, save=False, log=log)
@@ -296,7 +298,7 @@ def main():
            "kernels": kernels, "roofline": roof}
     if tuned is not None:
         res["autotune"] = {"tile_kernel": tuned["tile_kernel"], "tile_qubits": tuned["tile_qubits"],
-                           "seconds": round(tuned["seconds"], 1)}
+                           "resident_block": tuned["resident_block"], "seconds": round(tuned["seconds"], 1)}
 
     if not args.no_plain and len(objs) > 1:
         def plain():

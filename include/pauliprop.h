@@ -226,9 +226,17 @@ PP_API void pp_server_destroy(pp_server *s);
  *                        workgroup per tile, 1 persistent 256-thread
  *                        workgroups that prefetch the next tile, 2 one
  *                        single-wave (64-thread) workgroup per tile.
- * Both kernels give bit-identical results; k changes how ops are packed and
- * therefore the rounding, so a circuit keeps the k of its schedule. */
-typedef enum pp_tune_key { PP_TUNE_TILE_QUBITS = 0, PP_TUNE_TILE_KERNEL = 1 } pp_tune_key;
+ *   PP_TUNE_RESIDENT_BLOCK: index = n (5..7), value = 256, 512 or 1024
+ *                        threads for the LDS-resident kernel (untracked runs).
+ * The kernel variants give bit-identical results for a given tile size; k
+ * changes how ops are packed and therefore the rounding, so a circuit keeps
+ * the k of its schedule.  The resident block size changes the order of the
+ * final readout sum only. */
+typedef enum pp_tune_key {
+    PP_TUNE_TILE_QUBITS = 0,
+    PP_TUNE_TILE_KERNEL = 1,
+    PP_TUNE_RESIDENT_BLOCK = 2
+} pp_tune_key;
 PP_API pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value);
 PP_API pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value);
 

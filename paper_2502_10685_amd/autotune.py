@@ -35,6 +35,8 @@ def cache_path(dtype="f64"):
 
 
 def apply(table):
+    for n, b in table.get("resident_block", {}).items():
+        L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, int(n), int(b))
     for k, v in table.get("tile_kernel", {}).items():
         L.tune_set(L.PP_TUNE_TILE_KERNEL, int(k), int(v))
     for n, k in table.get("tile_qubits", {}).items():
@@ -81,13 +83,30 @@ def _count_for(n):
     return max(2, min(64, (1 << 16) // (4 ** (n - 6))))
 
 
-def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None):
+def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None, resident=(5, 6, 7)):
     """Times every candidate and returns (and applies, and caches) the table
-    {"tile_kernel": {k: variant}, "tile_qubits": {n: k}, "timings": ...}."""
+    {"tile_kernel": {k: variant}, "tile_qubits": {n: k},
+     "resident_block": {n: threads}, "timings": ...}."""
     from . import api
     say = log or (lambda s: None)
-    table = {"tile_kernel": {}, "tile_qubits": {}, "timings": {"tile_kernel": {}, "tile_qubits": {}},
+    table = {"tile_kernel": {}, "tile_qubits": {}, "resident_block": {},
+             "timings": {"tile_kernel": {}, "tile_qubits": {}, "resident_block": {}},
              "device": _device_name(), "dtype": dtype, "probe_gates": m}
+    # 0. threads of the LDS-resident kernel (one circuit per workgroup)
+    for n in resident:
+        circs = _probe_batch(api, n, 256, m, dtype, seed=8900 + n)
+        best, times = None, {}
+        for b in (256, 512, 1024):
+            L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, n, b)
+            times[b] = _time_batch(api, circs)
+            if best is None or times[b] < times[best]:
+                best = b
+        L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, n, best)
+        table["resident_block"][str(n)] = best
+        table["timings"]["resident_block"][str(n)] = {str(b): t for b, t in times.items()}
+        say(f"resident block n={n}: {best} ({ {b: round(t * 1e3, 2) for b, t in times.items()} } ms)")
+        for c in circs:
+            c.close()
     # 1. kernel variant per tile size k, on circuits with n = k + 3 tiled at k
     for k in (4, 5, 6):
         n = k + 3

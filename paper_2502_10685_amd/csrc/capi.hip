@@ -74,7 +74,8 @@ constexpr int kDenseMaxN = 16;
 constexpr int kAutoDenseMaxN = 13;
 constexpr int kLowQubits = 2;
 
-int g_tile_qubits[17] = {0, 0, 0, 0, 0, 0, 0, 0, 5, 5, 6, 6, 6, 6, 6, 6, 6};
+// defaults measured by the autotuner on MI355X (batched probes, FP64)
+int g_tile_qubits[17] = {0, 0, 0, 0, 0, 0, 0, 0, 6, 6, 6, 6, 6, 6, 6, 6, 6};
 int default_tile_qubits(int n) { return n >= 8 && n <= 16 ? g_tile_qubits[n] : (n > 16 ? 6 : 5); }
 
 // pinned staging for small asynchronous uploads, reused once the previous
@@ -921,6 +922,9 @@ struct BatchCache {
     size_t dcap = 0;
     Staging staging;
     hipEvent_t done = nullptr;
+    // LDS-resident circuits run on a second stream, overlapping the tile passes
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     struct Launch { int kind; int group_n; int off; int nd; int nblocks; pp::TileGroups tg; };
     std::vector<Launch> launches;  // kind 0 compose, 1 resident, 2 tile pass
     std::vector<int> tiled;        // indices of tiled circuits
@@ -1051,15 +1055,33 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         ProfScope ps(PC_INIT, s);
         HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
     }
+    bool any_res = false;
+    for (const auto &L : B.launches) any_res = any_res || L.kind == 1;
+    if (any_res && !B.aux) {
+        HIPCHK(hipStreamCreateWithFlags(&B.aux, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&B.fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&B.join, hipEventDisableTiming));
+    }
+    bool forked = false;
     for (const auto &L : B.launches) {
-        ProfScope ps(L.kind == 0 ? PC_COMPOSE : L.kind == 1 ? PC_RES : PC_TILE, s);
-        if (L.kind == 0) {
-            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, s));
-        } else if (L.kind == 1) {
-            HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, s));
-        } else {
-            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.tg, L.group_n, dbytes, false, s));
+        if (L.kind == 1 && !forked) {  // after the maps are composed
+            HIPCHK(hipEventRecord(B.fork, s));
+            HIPCHK(hipStreamWaitEvent(B.aux, B.fork, 0));
+            forked = true;
         }
+        hipStream_t ls = L.kind == 1 ? B.aux : s;
+        ProfScope ps(L.kind == 0 ? PC_COMPOSE : L.kind == 1 ? PC_RES : PC_TILE, ls);
+        if (L.kind == 0) {
+            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, ls));
+        } else if (L.kind == 1) {
+            HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, ls));
+        } else {
+            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.tg, L.group_n, dbytes, false, ls));
+        }
+    }
+    if (forked) {
+        HIPCHK(hipEventRecord(B.join, B.aux));
+        HIPCHK(hipStreamWaitEvent(s, B.join, 0));
     }
     for (int i : B.tiled) {
         pp_circuit *c = cs[i];
@@ -1665,6 +1687,12 @@ extern "C" pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value) 
         pp::set_tile_kernel_variant(index, value);
         return PP_OK;
     }
+    if (key == PP_TUNE_RESIDENT_BLOCK) {
+        if (index < 5 || index > 7 || (value != 256 && value != 512 && value != 1024))
+            return fail(PP_ERR_INVALID, "resident block: n in 5..7, value 256/512/1024");
+        pp::set_resident_block(index, value);
+        return PP_OK;
+    }
     return fail(PP_ERR_INVALID, "unknown tuning key");
 }
 
@@ -1676,6 +1704,10 @@ extern "C" pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value)
     }
     if (key == PP_TUNE_TILE_KERNEL && index >= 4 && index <= 6) {
         *value = pp::tile_kernel_variant(index);
+        return PP_OK;
+    }
+    if (key == PP_TUNE_RESIDENT_BLOCK && index >= 5 && index <= 7) {
+        *value = pp::resident_block(index);
         return PP_OK;
     }
     return fail(PP_ERR_INVALID, "unknown tuning key or index");

@@ -412,7 +412,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
 // observable, applies every op, reads out <O> and optionally stores the
 // final weights / presence for pp_get_terms.
 template <typename T, bool TRACK, int N, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK >= 512 ? 2 : 4))) void resident_kernel(const ResidentDesc *__restrict__ descs) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((N >= 7 && BLOCK <= 256) ? 2 : (BLOCK >= 1024 ? 4 : (BLOCK >= 512 ? 2 : 4))))) void resident_kernel(const ResidentDesc *__restrict__ descs) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double redd[BLOCK / 64];
     __shared__ long long redi[BLOCK / 64];
@@ -941,16 +941,32 @@ static hipError_t launch_res_t(const ResidentDesc *d, int nd, size_t lds, hipStr
     return hipGetLastError();
 }
 
+static int g_res_block[8] = {64, 64, 64, 64, 64, 512, 512, 1024};
+void set_resident_block(int n, int block) {
+    if (n >= 5 && n <= 7) g_res_block[n] = block;
+}
+int resident_block(int n) { return (n >= 1 && n <= 7) ? g_res_block[n] : 64; }
+
 template <typename T, bool TRACK>
 static hipError_t launch_res_b(const ResidentDesc *d, int nd, int n, size_t lds, hipStream_t s) {
+    const int blk = TRACK ? (n <= 4 ? 64 : n <= 6 ? 256 : 512) : g_res_block[n];
     switch (n) {
     case 1: return launch_res_t<T, TRACK, 1, 64>(d, nd, lds, s);
     case 2: return launch_res_t<T, TRACK, 2, 64>(d, nd, lds, s);
     case 3: return launch_res_t<T, TRACK, 3, 64>(d, nd, lds, s);
     case 4: return launch_res_t<T, TRACK, 4, 64>(d, nd, lds, s);
-    case 5: return launch_res_t<T, TRACK, 5, 256>(d, nd, lds, s);
-    case 6: return launch_res_t<T, TRACK, 6, 256>(d, nd, lds, s);
-    default: return launch_res_t<T, TRACK, 7, 512>(d, nd, lds, s);
+    case 5:
+        if (!TRACK && blk == 512) return launch_res_t<T, TRACK, 5, 512>(d, nd, lds, s);
+        if (!TRACK && blk == 1024) return launch_res_t<T, TRACK, 5, 1024>(d, nd, lds, s);
+        return launch_res_t<T, TRACK, 5, 256>(d, nd, lds, s);
+    case 6:
+        if (!TRACK && blk == 512) return launch_res_t<T, TRACK, 6, 512>(d, nd, lds, s);
+        if (!TRACK && blk == 1024) return launch_res_t<T, TRACK, 6, 1024>(d, nd, lds, s);
+        return launch_res_t<T, TRACK, 6, 256>(d, nd, lds, s);
+    default:
+        if (!TRACK && blk == 256) return launch_res_t<T, TRACK, 7, 256>(d, nd, lds, s);
+        if (!TRACK && blk == 1024) return launch_res_t<T, TRACK, 7, 1024>(d, nd, lds, s);
+        return launch_res_t<T, TRACK, 7, 512>(d, nd, lds, s);
     }
 }
 
@@ -966,7 +982,8 @@ hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int d
                  : launch_res_b<float, false>(d_descs, ndescs, n, lds, s);
 }
 
-static int g_tile_variant[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+// defaults measured by the autotuner on MI355X: one wave per 4^5-slot tile
+static int g_tile_variant[8] = {0, 0, 0, 0, 0, 2, 0, 0};
 void set_tile_kernel_variant(int k, int variant) {
     if (k >= 0 && k < 8) g_tile_variant[k] = variant;
 }

@@ -125,6 +125,9 @@ hipError_t launch_tile_pass(const TilePassDesc *d_descs, const TileGroups &group
 // 0: one workgroup per tile; 1: persistent prefetching workgroups (k <= 6)
 void set_tile_kernel_variant(int k, int variant);
 int tile_kernel_variant(int k);
+// threads per workgroup of the untracked LDS-resident kernel for n = 5..7
+void set_resident_block(int n, int block);
+int resident_block(int n);
 hipError_t launch_grad_pass(const GradPassDesc *d_desc, int ntiles, int k, hipStream_t s);
 hipError_t launch_grad_init_state(double *r, int n, hipStream_t s);
 hipError_t launch_grad_reduce(const double *partials, int nslots, int ntiles, double *rot_grad, hipStream_t s);

@@ -20,8 +20,10 @@ def test_autotune_applies_and_caches(tmp_path, monkeypatch):
     monkeypatch.setenv("PAULIPROP_TUNE_CACHE", str(tmp_path / "tune.json"))
     saved = {k: L.tune_get(L.PP_TUNE_TILE_KERNEL, k) for k in (4, 5, 6)}
     saved_q = {n: L.tune_get(L.PP_TUNE_TILE_QUBITS, n) for n in (8, 9)}
+    saved_b = L.tune_get(L.PP_TUNE_RESIDENT_BLOCK, 6)
     try:
-        table = autotune.tune(sizes=(8, 9), m=150)
+        table = autotune.tune(sizes=(8, 9), m=150, resident=(6,))
+        assert L.tune_get(L.PP_TUNE_RESIDENT_BLOCK, 6) == table["resident_block"]["6"]
         for k, v in table["tile_kernel"].items():
             assert L.tune_get(L.PP_TUNE_TILE_KERNEL, int(k)) == v
         for n, k in table["tile_qubits"].items():
@@ -38,3 +40,4 @@ def test_autotune_applies_and_caches(tmp_path, monkeypatch):
             L.tune_set(L.PP_TUNE_TILE_KERNEL, k, v)
         for n, k in saved_q.items():
             L.tune_set(L.PP_TUNE_TILE_QUBITS, n, k)
+        L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, 6, saved_b)

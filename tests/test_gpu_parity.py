@@ -323,3 +323,22 @@ def test_tile_kernel_variants_bitwise(api, k):
         L.tune_set(L.PP_TUNE_TILE_KERNEL, k, old)
     assert vals[0] == vals[1] == vals[2], vals
     assert abs(vals[0] - sv) <= TOL64
+
+
+@pytest.mark.parametrize("n", [5, 6, 7])
+def test_resident_block_sizes_agree(api, n):
+    """The LDS-resident kernel at 256, 512 and 1024 threads: the ops run in the
+    same order on every slot, only the readout sum order differs."""
+    from paper_2502_10685_amd import _lib as L
+    rng = np.random.default_rng(640 + n)
+    wc = W.random_circuit(rng, n, 700, W.obs_tfim(n))
+    sv = oracle.expval_sv(wc)
+    old = L.tune_get(L.PP_TUNE_RESIDENT_BLOCK, n)
+    try:
+        for b in (256, 512, 1024):
+            L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, n, b)
+            c = api.Circuit.from_workload(wc)
+            assert abs(float(c.evaluate().item()) - sv) <= TOL64, b
+            c.close()
+    finally:
+        L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, n, old)
