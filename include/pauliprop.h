@@ -170,8 +170,12 @@ PP_API pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_eve
                       double *d_grad);
 
 /* Copies the final string set of the last evaluation to host arrays in
- * canonical order (by z, then x), synchronizing `stream`.  DENSE requires
- * PP_OPT_TRACK_TERMS = 1 for that evaluation.  At most `capacity` strings are
+ * canonical order (by z, then x), synchronizing `stream`.  DENSE with
+ * PP_OPT_TRACK_TERMS = 1 for that evaluation returns the structural set (exact
+ * zero weights included, as the paper's expand/reduce keeps them); without it,
+ * the strings whose final weight is nonzero (tiled circuits only: an untracked
+ * LDS-resident evaluation, n <= 7, keeps its weights on chip and gives
+ * PP_ERR_STATE).  At most `capacity` strings are
  * written; *n_out receives the full count (PP_ERR_CAPACITY if larger). */
 PP_API pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *x, uint64_t *z,
                        double *coeff, int64_t *n_out);
@@ -225,7 +229,10 @@ PP_API void pp_server_destroy(pp_server *s);
  *   PP_TUNE_TILE_KERNEL: index = k (4..6), value = 0 one 256-thread
  *                        workgroup per tile, 1 persistent 256-thread
  *                        workgroups that prefetch the next tile, 2 one
- *                        single-wave (64-thread) workgroup per tile.
+ *                        single-wave (64-thread) workgroup per tile, 3
+ *                        (k = 6 only) one wave per tile holding the tile
+ *                        in registers, LDS used only to change which three
+ *                        qubits sit in registers.
  *   PP_TUNE_RESIDENT_BLOCK: index = n (5..7), value = 256, 512 or 1024
  *                        threads for the LDS-resident kernel (untracked runs).
  * The kernel variants give bit-identical results for a given tile size; k

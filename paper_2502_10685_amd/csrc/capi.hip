@@ -370,6 +370,12 @@ pp_status ensure_plan(pp_circuit *c) {
     } else {
         c->dplan = pp::plan_dense(c->g, k, kLowQubits, c->track == 0, c->track == 0);
         const pp::DensePlan &P = c->dplan;
+        {
+            // the kernels trust the schedule's digits and segment bounds
+            const std::string bad = pp::plan_check(P, c->n);
+            if (!bad.empty()) return fail(PP_ERR_STATE, "planner self-check: " + bad);
+            if (!c->track && !pp::plan_segmented(P)) return fail(PP_ERR_STATE, "planner self-check: unsegmented pass");
+        }
         if ((r = upload_vec(&c->d_ops, P.ops)) != PP_OK) return r;
         if ((r = upload_vec(&c->d_roff, P.roff)) != PP_OK) return r;
         if ((r = upload_vec(&c->d_rop, P.rop)) != PP_OK) return r;
@@ -413,6 +419,7 @@ pp_status ensure_plan(pp_circuit *c) {
                 d.ntiles = ntiles;
                 d.qubits = 0;
                 for (int j = 0; j < k; ++j) d.qubits |= (uint64_t)ps.qubit[j] << (8 * j);
+                d.reg_entry = pp::pass_reg_entry(P, ps);
                 c->h_pass.push_back(d);
             }
             if ((r = upload_vec(&c->d_pass, c->h_pass)) != PP_OK) return r;
@@ -439,7 +446,8 @@ void fill_plan_stats(pp_circuit *c) {
     s.engine = c->engine;
     if (c->engine == PP_ENGINE_DENSE) {
         const pp::DensePlan &P = c->dplan;
-        s.ops = (int64_t)P.ops.size();
+        s.ops = 0;
+        for (const pp::DOp &d : P.ops) s.ops += d.kind != pp::DOP_GROUP && d.kind != pp::DOP_SEG;
         s.passes = (int64_t)P.passes.size();
         s.tile_qubits = P.k;
         const int64_t slots = dense_slots(c->n);
@@ -620,9 +628,10 @@ pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *op, con
     pp::DensePlan P = pp::plan_dense(g, k, kLowQubits, compose != 0, reorder != 0);
     const std::string bad = pp::plan_check(P, n_qubits);
     if (!bad.empty()) return fail(PP_ERR_STATE, "planner self-check: " + bad);
+    if (compose && !pp::plan_segmented(P)) return fail(PP_ERR_STATE, "planner self-check: unsegmented pass");
     auto real_ops = [&](int b, int e) {
         int cnt = 0;
-        for (int i = b; i < e; ++i) cnt += P.ops[i].kind != pp::DOP_GROUP;
+        for (int i = b; i < e; ++i) cnt += P.ops[i].kind != pp::DOP_GROUP && P.ops[i].kind != pp::DOP_SEG;
         return cnt;
     };
     *n_ops = real_ops(0, (int)P.ops.size());
@@ -824,8 +833,9 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
     if (capacity > 0 && (!x || !z || !coeff)) return fail(PP_ERR_INVALID, "null output array");
     if (!c->evaluated) return fail(PP_ERR_STATE, "no evaluation yet");
     hipStream_t s = (hipStream_t)stream;
-    if (c->engine == PP_ENGINE_DENSE && !c->last_track)
-        return fail(PP_ERR_STATE, "DENSE needs PP_OPT_TRACK_TERMS = 1 for the evaluation");
+    if (c->engine == PP_ENGINE_DENSE && !c->last_track && c->dplan.resident)
+        return fail(PP_ERR_STATE, "an untracked LDS-resident evaluation keeps its weights on chip: set "
+                                  "PP_OPT_TRACK_TERMS = 1 for the evaluation");
     const uint64_t *sx = nullptr, *sz = nullptr;
     const void *sc = nullptr;
     int cbytes = c->dbytes;
@@ -863,7 +873,8 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
             tmp.x2 = (uint64_t *)tmp_base[3];
             tmp.z2 = (uint64_t *)tmp_base[4];
             tmp.c2 = tmp_base[5];
-            hipError_t e = pp::launch_dense_compact(c->coef, c->pres, c->n, c->dbytes, tmp.x, tmp.z, (double *)tmp.c,
+            hipError_t e = pp::launch_dense_compact(c->coef, c->last_track ? c->pres : nullptr, c->n, c->dbytes,
+                                                    tmp.x, tmp.z, (double *)tmp.c,
                                                     total, tmp.tile_flags, nullptr, nullptr, s);
             if (e == hipSuccess) {
                 hipLaunchKernelGGL(compact_to_sparse_count_kernel, dim3(1), dim3(64), 0, s, total, tmp.count);
@@ -1111,6 +1122,11 @@ pp_status ensure_grad(pp_circuit *c, int64_t every) {
     const int k_fwd = n <= 6 ? n : 6;
     G.plan = pp::plan_gradient(c->g, k_heis, k_fwd, kLowQubits, every);
     const pp::GradPlan &P = G.plan;
+    for (const pp::DensePlan *part : {&P.heis, &P.fwd}) {
+        const std::string bad = pp::plan_check(*part, n);
+        if (!bad.empty()) return fail(PP_ERR_STATE, "planner self-check: " + bad);
+    }
+    if (!pp::plan_segmented(P.heis)) return fail(PP_ERR_STATE, "planner self-check: unsegmented pass");
     pp_status r;
     if ((r = upload_vec(&G.hops, P.heis.ops)) != PP_OK) return r;
     if ((r = upload_vec(&G.hroff, P.heis.roff)) != PP_OK) return r;
@@ -1163,6 +1179,7 @@ pp_status ensure_grad(pp_circuit *c, int64_t every) {
             d.op_end = ps.op_end;
             d.ntiles = (int)((int64_t)1 << (2 * (n - k_heis)));
             for (int j = 0; j < k_heis; ++j) d.qubits |= (uint64_t)ps.qubit[j] << (8 * j);
+            d.reg_entry = pp::pass_reg_entry(P.heis, ps);
             td.push_back(d);
         }
         if ((r = upload_vec(&G.hpass, td)) != PP_OK) return r;
@@ -1683,7 +1700,8 @@ extern "C" pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value) 
         return PP_OK;
     }
     if (key == PP_TUNE_TILE_KERNEL) {
-        if (index < 4 || index > 6 || value < 0 || value > 2) return fail(PP_ERR_INVALID, "tile kernel: k in 4..6, value 0..2");
+        if (index < 4 || index > 6 || value < 0 || value > 4 || (value >= 3 && index != 6))
+            return fail(PP_ERR_INVALID, "tile kernel: k in 4..6, value 0..2 (3, 4: k = 6 only)");
         pp::set_tile_kernel_variant(index, value);
         return PP_OK;
     }

@@ -21,6 +21,7 @@
 // gates the pass holds.  Circuits with n <= 7 keep all 4^n slots in one
 // workgroup's LDS for the whole circuit.
 #include <algorithm>
+#include <type_traits>
 
 #include "pp_device.h"
 
@@ -385,6 +386,10 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
             const uint32_t w1 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[1]);
             const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, b = (w0 >> 16) & 0xff, ngates = (w0 >> 24) & 0xff;
             const unsigned smask = w1 & 0xffff, perm = w1 >> 16;
+            if (kind == DOP_SEG) {  // register-tile layout hint: nothing to do in LDS
+                ++i;
+                continue;
+            }
             if (kind == DOP_GROUP) {
                 if (i + 1 + ngates > cn) break;  // reload the chunk from this header
                 if constexpr (K >= 2) group_apply<T, K, BLOCK>(lc, a, b, oc, i + 1, ngates, tid);
@@ -638,6 +643,403 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
     }
 }
 
+// --------------------------------------------------- register tile kernel
+// One wave per 4^6-slot tile, the tile held in registers as FP64: lane l and
+// register e hold the slot whose local digits are the lane digits
+// (l0, l1, l2) = (l & 3, (l >> 2) & 3, l >> 4) and the register digits
+// (t0, t1, t2) = (e & 3, (e >> 2) & 3, e >> 4) of the current layout
+// (t0 < t1 < t2, l0 < l1 < l2 the other three).  The ops of a SEG segment act
+// on its register digits only, so a U1 is 16 register quads times a 3x3 map
+// and a CX is a fixed set of register moves; between segments the tile is
+// re-laid through LDS.  A layout whose register digits avoid local digits 0
+// and 1 has lanes 0-15 on 16 consecutive slots (128 bytes) and is loaded from
+// and stored to HBM directly.  Ops run in list order with the same FP64
+// expressions as the LDS kernels; FP32 weights are rounded where those
+// kernels store to LDS (after every op outside a GROUP and at the end of each
+// GROUP), so every launch shape gives bit-identical weights.
+struct RegLayout {
+    int t0, t1, t2, l0, l1, l2;
+};
+
+// Weights are read and written with buffer instructions: one resource per
+// tile (base = the tile's first slot), the lane's slot offset in a VGPR and
+// the register's in an SGPR, so the 64 accesses of a lane need no address
+// registers.  Both offsets are below 2^31 bytes when the tile's qubits are
+// all below 14 (the launcher only picks this kernel for n <= 14).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, -1, 0x00020000);
+}
+template <typename T>
+struct BufIO;
+template <>
+struct BufIO<double> {
+    typedef unsigned V __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+    }
+};
+template <>
+struct BufIO<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
+};
+
+__device__ __forceinline__ RegLayout reg_layout(unsigned triple) {
+    RegLayout L;
+    unsigned t = triple;
+    L.t0 = __builtin_ctz(t);
+    t &= t - 1;
+    L.t1 = __builtin_ctz(t);
+    t &= t - 1;
+    L.t2 = __builtin_ctz(t);
+    unsigned r = 0x3fu & ~triple;
+    L.l0 = __builtin_ctz(r);
+    r &= r - 1;
+    L.l1 = __builtin_ctz(r);
+    r &= r - 1;
+    L.l2 = __builtin_ctz(r);
+    return L;
+}
+
+// LDS word of the local index whose digit j is d, XOR-combined over digits.
+// The low four bits (the 8-byte bank) get a linear function of the digits
+// such that, read as GF(4)^2 = {(u, v)}, digits 0..5 contribute along the
+// lines {(x, 0)}, {(0, x)}, {(x, x)}, {(x, w x)}, {(x, w^2 x)}, {(x, w^2 x)};
+// distinct lines meet only in 0, so the 16 values of any two digits other
+// than the pair (4, 5) land on 16 distinct banks.  The first two lane digits
+// of a layout are never (4, 5), so every 16-lane quarter of a wave's access
+// is conflict-free.  The map is a bijection (bits 4 and up are kept).
+__device__ __forceinline__ int rsw_digit(int j, int d) {
+    const int w1 = ((d >> 1) & 1) | (((d ^ (d >> 1)) & 1) << 1);  // w d
+    const int w2 = ((d ^ (d >> 1)) & 1) | ((d & 1) << 1);         // w^2 d
+    const int v = j == 2 ? d : (j == 3 ? w1 : w2);
+    return (d << (2 * j)) ^ (j >= 2 ? (d | (v << 2)) : 0);
+}
+
+__device__ __forceinline__ int reg_lane_word(const RegLayout &L, int lane) {
+    return rsw_digit(L.l0, lane & 3) ^ rsw_digit(L.l1, (lane >> 2) & 3) ^ rsw_digit(L.l2, lane >> 4);
+}
+
+// e -> XOR of the basis words of its six bits (uniform)
+struct RegBasis {
+    int w[6];
+};
+__device__ __forceinline__ RegBasis reg_basis(const RegLayout &L) {
+    return RegBasis{{rsw_digit(L.t0, 1), rsw_digit(L.t0, 2), rsw_digit(L.t1, 1), rsw_digit(L.t1, 2),
+                     rsw_digit(L.t2, 1), rsw_digit(L.t2, 2)}};
+}
+__device__ __forceinline__ int reg_word(const RegBasis &B, int e) {
+    int o = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        if ((e >> j) & 1) o ^= B.w[j];
+    return o;
+}
+
+template <typename T>
+__device__ __forceinline__ void reg_relayout(double (&v)[64], T *lds, const RegLayout &A, const RegLayout &B,
+                                             int lane) {
+    // byte addresses: (word ^ word) * sizeof(T) = (bytes ^ bytes)
+    constexpr int S = sizeof(T) == 8 ? 3 : 2;
+    char *base = reinterpret_cast<char *>(lds);
+    {
+        const int lw = reg_lane_word(A, lane) << S;
+        RegBasis rb = reg_basis(A);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) rb.w[j] <<= S;
+#pragma unroll
+        for (int e = 0; e < 64; ++e) *reinterpret_cast<T *>(base + (lw ^ reg_word(rb, e))) = (T)v[e];
+    }
+    __syncthreads();
+    {
+        const int lw = reg_lane_word(B, lane) << S;
+        RegBasis rb = reg_basis(B);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) rb.w[j] <<= S;
+#pragma unroll
+        for (int e = 0; e < 64; ++e) v[e] = (double)*reinterpret_cast<const T *>(base + (lw ^ reg_word(rb, e)));
+    }
+    __syncthreads();
+}
+
+// Global slot offsets of a layout (lanes 0-15 must be local digits 0 and 1).
+struct RegGlobal {
+    long long lane;
+    long long w[6];
+};
+__device__ __forceinline__ RegGlobal reg_global(const RegLayout &L, uint64_t qubits, int lane) {
+    auto gq = [&](int j) { return 2 * (int)((qubits >> (8 * j)) & 0xff); };
+    RegGlobal G;
+    G.lane = ((long long)(lane & 3) << gq(L.l0)) | ((long long)((lane >> 2) & 3) << gq(L.l1)) |
+             ((long long)(lane >> 4) << gq(L.l2));
+    G.w[0] = 1ll << gq(L.t0);
+    G.w[1] = 2ll << gq(L.t0);
+    G.w[2] = 1ll << gq(L.t1);
+    G.w[3] = 2ll << gq(L.t1);
+    G.w[4] = 1ll << gq(L.t2);
+    G.w[5] = 2ll << gq(L.t2);
+    return G;
+}
+__device__ __forceinline__ long long reg_goff(const RegGlobal &G, int e) {
+    long long o = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        if ((e >> j) & 1) o += G.w[j];
+    return o;
+}
+
+// U1 on register digit P: the quads e + {1, 2, 3} * 4^P (X, Z, Y).
+template <int P>
+__device__ __forceinline__ void reg_u1(double (&v)[64], const double *__restrict__ M) {
+    constexpr int S = 1 << (2 * P);
+    const double m00 = M[0], m01 = M[1], m02 = M[2];
+    const double m10 = M[3], m11 = M[4], m12 = M[5];
+    const double m20 = M[6], m21 = M[7], m22 = M[8];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) {
+        if ((e >> (2 * P)) & 3) continue;
+        const double cx = v[e + S], cz = v[e + 2 * S], cy = v[e + 3 * S];
+        v[e + S] = m00 * cx + m01 * cy + m02 * cz;
+        v[e + 3 * S] = m10 * cx + m11 * cy + m12 * cz;
+        v[e + 2 * S] = m20 * cx + m21 * cy + m22 * cz;
+    }
+}
+
+template <int PC, int PT, int P>
+__device__ __forceinline__ void reg_cx_pair(double (&v)[64]) {
+    constexpr CxPairC pr = cx_pair_c(P);
+    constexpr int PR = 3 - PC - PT;
+#pragma unroll
+    for (int dr = 0; dr < 4; ++dr) {
+        const int e1 = (pr.dc1 << (2 * PC)) | (pr.dt1 << (2 * PT)) | (dr << (2 * PR));
+        const int e2 = (pr.dc2 << (2 * PC)) | (pr.dt2 << (2 * PT)) | (dr << (2 * PR));
+        const double t1 = v[e1], t2 = v[e2];
+        v[e1] = pr.neg ? -t2 : t2;
+        v[e2] = pr.neg ? -t1 : t1;
+    }
+}
+
+// CX with control on register digit PC and target on PT.
+template <int PC, int PT>
+__device__ __forceinline__ void reg_cx(double (&v)[64]) {
+    reg_cx_pair<PC, PT, 0>(v);
+    reg_cx_pair<PC, PT, 1>(v);
+    reg_cx_pair<PC, PT, 2>(v);
+    reg_cx_pair<PC, PT, 3>(v);
+    reg_cx_pair<PC, PT, 4>(v);
+    reg_cx_pair<PC, PT, 5>(v);
+}
+
+__device__ __forceinline__ double lane_read_f64(double x, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ void reg_round(double (&v)[64]) {
+    if constexpr (!std::is_same<T, double>::value) {
+#pragma unroll
+        for (int e = 0; e < 64; ++e) v[e] = (double)(T)v[e];
+    }
+}
+
+// Where a tile of a launch lives: its descriptor fields and slot base.
+struct RegTile {
+    void *coef;
+    const DOp *ops;
+    const double *maps;
+    long long base;
+    uint64_t qubits;
+    int o0, o1;
+    unsigned entry;
+};
+
+__device__ __forceinline__ RegTile reg_locate(const TilePassDesc *__restrict__ descs, const TileGroups &grp, int b) {
+    int gi = 0;
+    while (gi + 1 < grp.ngroups && b >= grp.first_block[gi + 1]) ++gi;
+    const int rel = b - grp.first_block[gi];
+    const TilePassDesc &d = descs[grp.first_desc[gi] + (rel >> grp.shift[gi])];
+    RegTile t;
+    t.coef = d.coef;
+    t.ops = d.ops;
+    t.maps = d.maps;
+    t.qubits = d.qubits;
+    t.o0 = d.op_begin;
+    t.o1 = d.op_end;
+    t.entry = d.reg_entry;
+    if (__builtin_popcount(t.entry) != 3 || (t.entry & ~0x3cu)) t.entry = 0x38u;
+    unsigned inmask = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) inmask |= 1u << (unsigned)((t.qubits >> (8 * j)) & 0xff);
+    long long base = 0, rest = rel & ((1 << grp.shift[gi]) - 1);
+    const int n = d.n;
+    for (int q = 0; q < n; ++q) {
+        if ((inmask >> q) & 1u) continue;
+        base |= (rest & 3ll) << (2 * q);
+        rest >>= 2;
+    }
+    t.base = base;
+    return t;
+}
+
+// Op entries [cb, cb + 64) of a pass, one per lane, with the map of a U1.
+struct RegOps {
+    uint32_t w0, w1, w2;
+    double m[9];
+};
+__device__ __forceinline__ void reg_load_ops(RegOps &r, const RegTile &t, int cb, int lane) {
+    const int i = cb + lane;
+    if (i < t.o1) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(t.ops + i);
+        r.w0 = w[0];
+        r.w1 = w[1];
+        r.w2 = w[2];
+        if ((r.w0 & 0xff) == DOP_U1) {
+            const double *src = t.maps + 9ull * r.w2;
+#pragma unroll
+            for (int j = 0; j < 9; ++j) r.m[j] = src[j];
+        }
+    }
+}
+
+template <typename T, typename V>
+__device__ __forceinline__ void reg_load_tile(V (&v)[64], const RegTile &t, int lane) {
+    const RegLayout L = reg_layout(t.entry);
+    const RegGlobal G = reg_global(L, t.qubits, lane);
+    const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(t.coef) + t.base);
+    const unsigned lo = (unsigned)G.lane * (unsigned)sizeof(T);
+#pragma unroll
+    for (int e = 0; e < 64; ++e) v[e] = (V)BufIO<T>::ld(rs, lo, (unsigned)reg_goff(G, e) * (unsigned)sizeof(T));
+}
+
+// Persistent: a grid of at most (co-resident waves) single-wave workgroups
+// walks the launch's tiles with stride gridDim.x; while a wave runs the ops
+// of one tile, the loads of its next tile (and that pass's op entries) are
+// in flight, so HBM latency overlaps the register work.
+template <typename T, bool PF>
+__global__ __launch_bounds__(64) void tile_reg_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) {
+    __shared__ __align__(16) T lds[1 << 12];  // the launch's only LDS: byte address = offset
+    const int total = grp.first_block[grp.ngroups];
+    const int lane = threadIdx.x;
+    int blk = blockIdx.x;
+    if (blk >= total) return;
+    RegTile cur = reg_locate(descs, grp, blk);
+    RegOps oc;
+    oc.w0 = oc.w1 = oc.w2 = 0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) oc.m[j] = 0.0;
+    reg_load_ops(oc, cur, cur.o0, lane);
+    double v[64];
+    reg_load_tile<T>(v, cur, lane);
+    for (;;) {
+        const int nblk = blk + (int)gridDim.x;
+        const bool has_next = nblk < total;
+        RegTile nxt = cur;
+        RegOps on = oc;
+        T pre[64];
+        if (has_next) {
+            nxt = reg_locate(descs, grp, nblk);
+            if (PF) {
+                reg_load_ops(on, nxt, nxt.o0, lane);
+                reg_load_tile<T>(pre, nxt, lane);
+            }
+        }
+        // ---- the ops of the current tile, in registers: one flat dispatch
+        // per entry (a single join point keeps one register assignment)
+        constexpr unsigned kHbmTriple = 0x38u;  // digits 3, 4, 5 in registers
+        unsigned lay = cur.entry;
+        RegLayout L = reg_layout(lay);
+        int cb = cur.o0, grp_left = 0;
+        for (int i = cur.o0; i < cur.o1; ++i) {
+            if (i - cb >= 64) {
+                cb = i;
+                reg_load_ops(oc, cur, cb, lane);
+            }
+            const int li = i - cb;
+            const uint32_t w0 = __builtin_amdgcn_readlane(oc.w0, li);
+            const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, bd = (w0 >> 16) & 0xff;
+            int code = 0;  // 0 nothing, 1-3 U1 on register digit 0-2, 4-9 CX, 10 re-layout
+            bool rnd = false;
+            unsigned next = lay;
+            if (kind == DOP_SEG) {
+                const uint32_t w1 = __builtin_amdgcn_readlane(oc.w1, li);
+                next = (1u << a) | (1u << bd) | (1u << (w1 & 0xffff));
+                code = next != lay ? 10 : 0;
+            } else if (kind == DOP_GROUP) {
+                grp_left = (w0 >> 24) & 0xff;
+            } else {
+                const int pa = a == L.t0 ? 0 : (a == L.t1 ? 1 : 2);
+                if (kind == DOP_U1) {
+                    code = 1 + pa;
+                } else {
+                    const int pb = bd == L.t0 ? 0 : (bd == L.t1 ? 1 : 2);
+                    // (pa, pb) = (0,1) (0,2) (1,0) (1,2) (2,0) (2,1) -> 4..9
+                    code = 4 + 2 * pa + (pb > pa ? pb - 1 : pb);
+                }
+                if (grp_left > 0) rnd = --grp_left == 0;
+                else rnd = kind == DOP_U1;
+            }
+            double M[9];
+            if (code >= 1 && code <= 3) {
+#pragma unroll
+                for (int j = 0; j < 9; ++j) M[j] = lane_read_f64(oc.m[j], li);
+            }
+            switch (code) {
+            case 1: reg_u1<0>(v, M); break;
+            case 2: reg_u1<1>(v, M); break;
+            case 3: reg_u1<2>(v, M); break;
+            case 4: reg_cx<0, 1>(v); break;
+            case 5: reg_cx<0, 2>(v); break;
+            case 6: reg_cx<1, 0>(v); break;
+            case 7: reg_cx<1, 2>(v); break;
+            case 8: reg_cx<2, 0>(v); break;
+            case 9: reg_cx<2, 1>(v); break;
+            case 10: {
+                const RegLayout N = reg_layout(next);
+                reg_relayout<T>(v, lds, L, N, lane);
+                L = N;
+                lay = next;
+                break;
+            }
+            default: break;
+            }
+            if (rnd) reg_round<T>(v);
+        }
+        if (lay & 3u) {
+            const RegLayout N = reg_layout(kHbmTriple);
+            reg_relayout<T>(v, lds, L, N, lane);
+            L = N;
+        }
+        {
+            const RegGlobal G = reg_global(L, cur.qubits, lane);
+            const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(cur.coef) + cur.base);
+            const unsigned lo = (unsigned)G.lane * (unsigned)sizeof(T);
+#pragma unroll
+            for (int e = 0; e < 64; ++e) BufIO<T>::st(rs, lo, (unsigned)reg_goff(G, e) * (unsigned)sizeof(T), (T)v[e]);
+        }
+        if (!has_next) break;
+        blk = nblk;
+        cur = nxt;
+        if (PF) {
+            oc = on;
+#pragma unroll
+            for (int e = 0; e < 64; ++e) v[e] = (double)pre[e];
+        } else {
+            reg_load_ops(oc, cur, cur.o0, lane);
+            reg_load_tile<T>(v, cur, lane);
+        }
+    }
+}
+
 // ------------------------------------------------------ adjoint sweep
 // Forward propagation of the observable weights c and the state
 // coefficients r through one pass.  U1 ops hold the Heisenberg matrix M of a
@@ -848,12 +1250,21 @@ __global__ __launch_bounds__(256) void dense_count_kernel(const uint8_t *pres, l
 // per-block counts, one exclusive scan, then ordered writes.
 constexpr int CMP_CHUNK = 4096;
 
-__global__ __launch_bounds__(256) void compact_count_kernel(const uint8_t *pres, long long size, int *counts) {
+// A slot is kept when its presence byte is set, or, without presence bytes
+// (untracked runs), when its weight is nonzero.
+template <typename T>
+__device__ __forceinline__ bool slot_kept(const T *coef, const uint8_t *pres, long long i) {
+    return pres ? pres[i] != 0 : coef[i] != (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void compact_count_kernel(const T *coef, const uint8_t *pres, long long size,
+                                                            int *counts) {
     __shared__ long long redi[4];
     const long long b0 = (long long)blockIdx.x * CMP_CHUNK;
     long long mine = 0;
     for (int i = threadIdx.x; i < CMP_CHUNK; i += 256)
-        if (b0 + i < size) mine += pres[b0 + i];
+        if (b0 + i < size) mine += slot_kept(coef, pres, b0 + i);
     const long long tot = block_sum_i<256>(mine, redi);
     if (threadIdx.x == 0) counts[blockIdx.x] = (int)tot;
 }
@@ -881,7 +1292,7 @@ __global__ __launch_bounds__(256) void compact_write_kernel(const T *coef, const
     __syncthreads();
     for (int r = 0; r < CMP_CHUNK; r += 256) {
         const long long i = b0 + r + threadIdx.x;
-        const bool p = i < size && pres[i];
+        const bool p = i < size && slot_kept(coef, pres, i);
         const unsigned long long bal = __ballot(p);
         const int below = __popcll(bal & ((1ull << lane) - 1ull));
         if (lane == 0) wcount[w] = __popcll(bal);
@@ -1001,6 +1412,29 @@ int num_cus() {
 template <typename T, bool TRACK, int K>
 static hipError_t launch_tile_t(const TilePassDesc *d, const TileGroups &grp, size_t lds, hipStream_t s) {
     const int nblocks = grp.first_block[grp.ngroups];
+    // the register-tile kernel's 32-bit buffer offsets hold registers of at
+    // most 14 qubits; every group of a launch shares one n = k + shift / 2
+    int max_n = K;
+    for (int gi = 0; gi < grp.ngroups; ++gi) max_n = std::max(max_n, K + grp.shift[gi] / 2);
+    if (!TRACK && K == 6 && g_tile_variant[6] == 3 && max_n <= 14) {
+        // one wave per tile, tile in registers; LDS only for re-layouts
+        hipLaunchKernelGGL((tile_reg_kernel<T, false>), dim3(nblocks), dim3(64), 0, s, d, grp);
+        return hipGetLastError();
+    }
+    if (!TRACK && K == 6 && g_tile_variant[6] == 4 && max_n <= 14) {
+        // the same, persistent: as many single-wave workgroups as fit at
+        // once, each loading its next tile while it works on the current one
+        auto fn = tile_reg_kernel<T, true>;
+        static int resident = 0;
+        if (!resident) {
+            int per_cu = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 64, 0);
+            if (e != hipSuccess) return e;
+            resident = std::max(per_cu, 1) * num_cus();
+        }
+        hipLaunchKernelGGL(fn, dim3(std::min(nblocks, resident)), dim3(64), 0, s, d, grp);
+        return hipGetLastError();
+    }
     if (!TRACK && K <= 6 && g_tile_variant[K] == 2) {
         auto fn = tile_kernel<T, false, (K <= 6 ? K : 6), 64>;
         static bool attr64 = false;
@@ -1153,7 +1587,12 @@ hipError_t launch_dense_compact(const void *coef, const uint8_t *pres, int n, in
                                 unsigned long long *, int *, hipStream_t s) {
     const long long size = 1ll << (2 * n);
     const int nb = (int)((size + CMP_CHUNK - 1) / CMP_CHUNK);
-    hipLaunchKernelGGL(compact_count_kernel, dim3(nb), dim3(256), 0, s, pres, size, block_counts);
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(compact_count_kernel<double>, dim3(nb), dim3(256), 0, s, (const double *)coef, pres, size,
+                           block_counts);
+    else
+        hipLaunchKernelGGL(compact_count_kernel<float>, dim3(nb), dim3(256), 0, s, (const float *)coef, pres, size,
+                           block_counts);
     hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(64), 0, s, block_counts, nb, count);
     if (dtype_bytes == 8)
         hipLaunchKernelGGL(compact_write_kernel<double>, dim3(nb), dim3(256), 0, s, (const double *)coef, pres, size,

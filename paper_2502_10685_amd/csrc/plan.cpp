@@ -59,12 +59,12 @@ namespace {
 
 unsigned op_digits(const DOp &d) { return d.kind == DOP_CX ? (1u << d.a) | (1u << d.b) : (1u << d.a); }
 
-// Regroups ops [b, e) of P.ops: repeatedly takes the first remaining op and
-// every later op whose digits stay within one pair of digits and that does
-// not share a digit with an op it would move past (ops on disjoint digits
+// Regroups a run of ops: repeatedly takes the first remaining op and every
+// later op whose digits stay within one pair of digits and that does not
+// share a digit with an op it would move past (ops on disjoint digits
 // commute).  Groups of two or more ops get a GROUP header.
-void group_pass(DensePlan &P, int b, int e, int k) {
-    std::vector<DOp> in(P.ops.begin() + b, P.ops.begin() + e), out;
+std::vector<DOp> group_ops(const std::vector<DOp> &in, int k) {
+    std::vector<DOp> out;
     std::vector<char> used(in.size(), 0);
     for (size_t i = 0; i < in.size(); ++i) {
         if (used[i]) continue;
@@ -105,8 +105,70 @@ void group_pass(DensePlan &P, int b, int e, int k) {
         out.push_back(h);
         for (size_t j : mem) out.push_back(in[j]);
     }
-    P.ops.erase(P.ops.begin() + b, P.ops.begin() + e);
-    P.ops.insert(P.ops.begin() + b, out.begin(), out.end());
+    return out;
+}
+
+// Orders the ops of a k = kSegTileDigits pass into register segments: the
+// same greedy rule as group_ops with up to three digits per segment.  Each
+// segment opens with a SEG header naming its digit triple (a < b < smask)
+// and the number of entries that follow (GROUP headers included); inside a
+// segment ops on a common digit pair are packed into GROUP ops.  A triple
+// with spare digits is completed with the previous segment's digits (no
+// re-layout between the two) and otherwise with digits 2..5 when the
+// segment avoids digits 0 and 1 (a layout that can be loaded from and
+// stored to HBM directly).
+std::vector<DOp> segment_ops(const std::vector<DOp> &in, int k) {
+    std::vector<DOp> out;
+    std::vector<char> used(in.size(), 0);
+    unsigned prev = 0;
+    for (size_t i = 0; i < in.size(); ++i) {
+        if (used[i]) continue;
+        unsigned set = op_digits(in[i]), skipped = 0;
+        std::vector<DOp> mem{in[i]};
+        used[i] = 1;
+        for (size_t j = i + 1; j < in.size(); ++j) {
+            if (used[j]) continue;
+            const unsigned d = op_digits(in[j]);
+            if (d & skipped) {
+                skipped |= d;
+                continue;
+            }
+            if (__builtin_popcount(set | d) <= 3) {
+                set |= d;
+                mem.push_back(in[j]);
+                used[j] = 1;
+            } else {
+                skipped |= d;
+            }
+        }
+        if (__builtin_popcount(set | prev) == 3) set |= prev;
+        const unsigned pref = (set & 3u) ? 0u : 0x3cu;
+        for (int q = 0; q < k && __builtin_popcount(set) < 3; ++q)
+            if ((pref >> q) & 1u) set |= 1u << q;
+        for (int q = 0; q < k && __builtin_popcount(set) < 3; ++q) set |= 1u << q;
+        prev = set;
+        const std::vector<DOp> body = group_ops(mem, k);
+        // SEG headers count at most 255 entries; a GROUP stays with its members
+        size_t b = 0;
+        while (b < body.size()) {
+            size_t e = b;
+            while (e < body.size()) {
+                const size_t unit = body[e].kind == DOP_GROUP ? 1 + body[e].ngates : 1;
+                if (e + unit - b > 255) break;
+                e += unit;
+            }
+            DOp h{};
+            h.kind = DOP_SEG;
+            h.a = (uint8_t)__builtin_ctz(set);
+            h.b = (uint8_t)__builtin_ctz(set & (set - 1));
+            h.smask = (uint16_t)(31 - __builtin_clz(set));
+            h.ngates = (uint8_t)(e - b);
+            out.push_back(h);
+            out.insert(out.end(), body.begin() + b, body.begin() + e);
+            b = e;
+        }
+    }
+    return out;
 }
 
 void group_all(DensePlan &P) {
@@ -114,9 +176,12 @@ void group_all(DensePlan &P) {
     for (DensePass &ps : P.passes) {
         ps.op_begin += shift;
         ps.op_end += shift;
-        const int before = (int)P.ops.size();
-        group_pass(P, ps.op_begin, ps.op_end, ps.k);
-        const int added = (int)P.ops.size() - before;
+        const std::vector<DOp> in(P.ops.begin() + ps.op_begin, P.ops.begin() + ps.op_end);
+        const std::vector<DOp> out =
+            (!P.resident && ps.k == kSegTileDigits) ? segment_ops(in, ps.k) : group_ops(in, ps.k);
+        P.ops.erase(P.ops.begin() + ps.op_begin, P.ops.begin() + ps.op_end);
+        P.ops.insert(P.ops.begin() + ps.op_begin, out.begin(), out.end());
+        const int added = (int)out.size() - (int)in.size();
         ps.op_end += added;
         shift += added;
     }
@@ -356,14 +421,33 @@ std::string plan_check(const DensePlan &P, int n) {
         if (k < 1 || k > n || (k < n && k > 8)) return "bad tile size";
         for (int j = 1; j < k && j < 8; ++j)
             if (ps.qubit[j] <= ps.qubit[j - 1] || ps.qubit[j] >= n) return "tile qubits not ascending";
+        const bool segmented = ps.op_begin < ps.op_end && P.ops[ps.op_begin].kind == DOP_SEG;
+        if (segmented && (P.resident || k != kSegTileDigits)) return "SEG header outside a register-tile pass";
+        int seg_end = ps.op_begin;
+        unsigned triple = 0;
         for (int i = ps.op_begin; i < ps.op_end; ++i) {
             const DOp &d = P.ops[i];
+            if (d.kind == DOP_SEG) {
+                if (!segmented || i != seg_end) return "SEG header inside a segment";
+                if (!(d.a < d.b && d.b < d.smask && d.smask < k) || d.ngates < 1 || i + d.ngates >= ps.op_end)
+                    return "bad SEG header";
+                triple = (1u << d.a) | (1u << d.b) | (1u << d.smask);
+                seg_end = i + 1 + d.ngates;
+                continue;
+            }
+            if (segmented && i >= seg_end) return "op outside every SEG";
+            if (segmented) {
+                const unsigned dg = d.kind == DOP_CX ? (1u << d.a) | (1u << d.b) : (1u << d.a);
+                if (d.kind != DOP_GROUP && (dg & ~triple)) return "op digit outside its SEG triple";
+                if (d.kind == DOP_GROUP && i + d.ngates >= seg_end) return "GROUP crosses a SEG boundary";
+            }
             if (d.kind == DOP_GROUP) {
                 if (d.a == d.b || d.a >= k || d.b >= k || d.ngates < 2 || i + d.ngates >= ps.op_end)
                     return "bad GROUP header";
                 for (int j = i + 1; j <= i + d.ngates; ++j) {
                     const DOp &m = P.ops[j];
-                    if (m.kind == DOP_GROUP) return "nested GROUP";
+                    if (m.kind == DOP_GROUP || m.kind == DOP_SEG) return "nested GROUP";
+                    if (segmented && (op_digits(m) & ~triple)) return "op digit outside its SEG triple";
                     if (m.a != d.a && m.a != d.b) return "GROUP member outside its pair";
                     if (m.kind == DOP_CX && ((m.b != d.a && m.b != d.b) || m.a == m.b)) return "GROUP CX outside its pair";
                     if (m.kind == DOP_U1 && m.map >= (uint32_t)P.nmaps()) return "map index out of range";
@@ -377,6 +461,22 @@ std::string plan_check(const DensePlan &P, int n) {
     }
     if (expect != (int)P.ops.size()) return "ops outside every pass";
     return "";
+}
+
+uint32_t pass_reg_entry(const DensePlan &P, const DensePass &ps) {
+    if (ps.op_begin < ps.op_end && P.ops[ps.op_begin].kind == DOP_SEG) {
+        const DOp &h = P.ops[ps.op_begin];
+        const uint32_t t = (1u << h.a) | (1u << h.b) | (1u << h.smask);
+        if (!(t & 3u)) return t;
+    }
+    return 0x38u;
+}
+
+bool plan_segmented(const DensePlan &P) {
+    for (const DensePass &ps : P.passes)
+        if (!P.resident && ps.k == kSegTileDigits && ps.op_begin < ps.op_end && P.ops[ps.op_begin].kind != DOP_SEG)
+            return false;
+    return true;
 }
 
 void plan_append(DensePlan &all, const DensePlan &part) {

@@ -52,6 +52,9 @@ struct SparsePlan {
 // contain the lowest `low` qubits.
 DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder);
 constexpr int kMaxGroupOps = 16;
+// Tile size of the register-tile kernel: its passes are ordered into SEG
+// segments (see segment_ops in plan.cpp).
+constexpr int kSegTileDigits = 6;
 
 // General form: gates [g_begin, g_end) only; forward = g_begin first (the
 // adjoint sweep) instead of Heisenberg order; slot (optional, size m): for
@@ -72,6 +75,15 @@ DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &
 // on them, passes tile the op list, digits are below the tile size, map
 // indices are in range.  Returns an empty string or the first violation.
 std::string plan_check(const DensePlan &P, int n);
+
+// True when every non-empty tiled pass of kSegTileDigits qubits opens with a
+// SEG header (the register-tile kernel can run it).
+bool plan_segmented(const DensePlan &P);
+
+// Digit triple (bit mask) the register-tile kernel loads a pass into: the
+// first segment's triple when it avoids digits 0 and 1 (lanes then cover 16
+// consecutive slots), else digits 3, 4, 5.
+uint32_t pass_reg_entry(const DensePlan &P, const DensePass &ps);
 
 // Appends `part` to `all`, offsetting op, map and recipe indices.
 void plan_append(DensePlan &all, const DensePlan &part);

@@ -13,13 +13,17 @@ namespace pp {
 // i.e. qubit q owns the base-4 digit q (digit value x + 2z: I=0 X=1 Z=2 Y=3).
 // This is the paper's index space 0 ... 4^n - 1 (Sec. III-B) with a digit
 // order that makes a qubit's four letters one digit of the slot index.
-enum : uint8_t { DOP_U1 = 0, DOP_CX = 1, DOP_GROUP = 2 };
+enum : uint8_t { DOP_U1 = 0, DOP_CX = 1, DOP_GROUP = 2, DOP_SEG = 3 };
 
 // One device operation on an LDS tile.  U1: a composed single-qubit map on
 // local digit a (a real 3x3 matrix over the X, Y, Z weights, I is fixed).
 // CX: control digit a, target digit b.  GROUP: header of the next ngates ops,
 // which act only on digits a and b; a thread applies all of them to each
-// 16-slot block of those two digits in registers.  16 bytes, read uniformly.
+// 16-slot block of those two digits in registers.  SEG: header of the next
+// ngates entries (GROUP headers included), whose ops act only on the digit
+// triple a < b < smask; the register-tile kernel holds those three digits in
+// registers for the whole segment, the LDS kernels skip the header.  16
+// bytes, read uniformly.
 struct DOp {
     uint8_t kind;
     uint8_t a, b;
@@ -60,6 +64,8 @@ struct TilePassDesc {
     int32_t tile_begin;            // first block of this desc in the launch
     int32_t ntiles;
     uint64_t qubits;               // byte j = global qubit of local digit j (ascending)
+    uint32_t reg_entry;            // register-tile kernel: digit triple (bit mask) to load into registers
+    uint32_t reserved;
 };
 
 // One pass of the adjoint sweep over tiles of 4^k slots (k = n: one tile).

@@ -342,3 +342,86 @@ def test_resident_block_sizes_agree(api, n):
             c.close()
     finally:
         L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, n, old)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [8, 9, 10])
+def test_register_tile_kernel_bitwise(api, n, dtype):
+    """The register-tile kernel (one wave per 4^6-slot tile, the tile held in
+    registers, LDS only between digit-triple segments) against the 256-thread
+    LDS kernel: same ops, same order, same FP32 rounding points, so every
+    weight is identical bit for bit; both match the state vector."""
+    from paper_2502_10685_amd import _lib as L
+    rng = np.random.default_rng(660 + n)
+    wc = W.random_circuit(rng, n, 1500, W.obs_tfim(n))
+    sv = oracle.expval_sv(wc)
+    tol = TOL64 if dtype == "f64" else TOL32
+    old = L.tune_get(L.PP_TUNE_TILE_KERNEL, 6)
+    res = []
+    try:
+        for variant in (0, 3, 4):
+            L.tune_set(L.PP_TUNE_TILE_KERNEL, 6, variant)
+            print(f"register tile n={n} {dtype} variant={variant}", flush=True)
+            c = api.Circuit.from_workload(wc, engine="dense", tile_qubits=6, dtype=dtype)
+            ev = float(c.evaluate().item())
+            x, z, cf = c.terms()
+            res.append((ev, x, z, cf))
+            c.close()
+    finally:
+        L.tune_set(L.PP_TUNE_TILE_KERNEL, 6, old)
+    e0, x0, z0, c0 = res[0]
+    for e3, x3, z3, c3 in res[1:]:
+        assert e0 == e3
+        assert np.array_equal(x0, x3) and np.array_equal(z0, z3)
+        assert np.array_equal(c0.view(np.uint64), c3.view(np.uint64))
+    assert abs(e0 - sv) <= tol
+
+
+@pytest.mark.parametrize("n", [14, 15])
+def test_register_tile_kernel_largest_registers(api, n):
+    """n = 14 is the largest register the register-tile kernel takes (its
+    buffer offsets reach 2^31 bytes at FP64); at n = 15 the launcher runs the
+    LDS kernel instead.  Both settings agree bit for bit and match the state
+    vector."""
+    from paper_2502_10685_amd import _lib as L
+    rng = np.random.default_rng(657 + n)
+    wc = W.random_circuit(rng, n, 90, W.obs_z(n, [0, n - 1]))
+    sv = oracle.expval_sv(wc)
+    old = L.tune_get(L.PP_TUNE_TILE_KERNEL, 6)
+    vals = []
+    try:
+        for variant in (0, 3, 4):
+            L.tune_set(L.PP_TUNE_TILE_KERNEL, 6, variant)
+            print(f"register tile n={n} variant={variant}", flush=True)
+            c = api.Circuit.from_workload(wc, engine="dense", tile_qubits=6)
+            vals.append(float(c.evaluate().item()))
+            c.close()
+    finally:
+        L.tune_set(L.PP_TUNE_TILE_KERNEL, 6, old)
+    assert vals[0] == vals[1] == vals[2], vals
+    assert abs(vals[1] - sv) <= TOL64
+
+
+def test_untracked_dense_terms_are_the_nonzero_weights(api):
+    """Without term tracking a tiled DENSE evaluation reports the strings of
+    nonzero final weight: they match the tracked structural set up to the
+    exact zeros, weight by weight; an untracked LDS-resident run refuses."""
+    from paper_2502_10685_amd._lib import PauliPropError
+    rng = np.random.default_rng(680)
+    wc = W.random_circuit(rng, 8, 600, W.obs_tfim(8))
+    ct = api.Circuit.from_workload(wc, engine="dense", track=True)
+    ct.evaluate()
+    xt, zt, cft = ct.terms()
+    cu = api.Circuit.from_workload(wc, engine="dense")
+    cu.evaluate()
+    xu, zu, cfu = cu.terms()
+    assert np.all(cfu != 0.0)
+    tr = {(int(a), int(b)): float(w) for a, b, w in zip(xt, zt, cft)}
+    un = {(int(a), int(b)): float(w) for a, b, w in zip(xu, zu, cfu)}
+    assert set(un) <= set(tr)
+    assert all(key in un for key, w in tr.items() if abs(w) > 1e-9)
+    assert max(abs(tr[key] - un.get(key, 0.0)) for key in tr) <= TOL64
+    small = api.Circuit.from_workload(W.config1())
+    small.evaluate()
+    with pytest.raises(PauliPropError):
+        small.terms()
