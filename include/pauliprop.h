@@ -232,7 +232,11 @@ PP_API void pp_server_destroy(pp_server *s);
  *                        single-wave (64-thread) workgroup per tile, 3
  *                        (k = 6 only) one wave per tile holding the tile
  *                        in registers, LDS used only to change which three
- *                        qubits sit in registers.
+ *                        qubits sit in registers, 4 (k = 6 only) the same,
+ *                        persistent, prefetching the next tile.  Variants
+ *                        1, 3 and 4 serve launches whose circuits have
+ *                        n <= 14 (32-bit buffer offsets); larger ones run
+ *                        variant 0.
  *   PP_TUNE_RESIDENT_BLOCK: index = n (5..7), value = 256, 512 or 1024
  *                        threads for the LDS-resident kernel (untracked runs).
  * The kernel variants give bit-identical results for a given tile size; k

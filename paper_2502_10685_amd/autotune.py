@@ -18,7 +18,8 @@ import numpy as np
 
 from . import _lib as L
 
-VARIANT_NAMES = {0: "workgroup-per-tile", 1: "persistent-prefetch", 2: "wave-per-tile"}
+VARIANT_NAMES = {0: "workgroup-per-tile", 1: "persistent-prefetch", 2: "wave-per-tile",
+                 3: "register-tile", 4: "register-tile-prefetch"}
 
 
 def _device_name():
@@ -112,7 +113,7 @@ def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None, res
         n = k + 3
         circs = _probe_batch(api, n, _count_for(n), m, dtype, seed=9000 + k, tile_qubits=k)
         best, times = None, {}
-        for v in (0, 1, 2):
+        for v in ((0, 1, 2, 3, 4) if k == 6 else (0, 1, 2)):
             L.tune_set(L.PP_TUNE_TILE_KERNEL, k, v)
             times[v] = _time_batch(api, circs)
             if best is None or times[v] < times[best]:

@@ -1701,7 +1701,7 @@ extern "C" pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value) 
     }
     if (key == PP_TUNE_TILE_KERNEL) {
         if (index < 4 || index > 6 || value < 0 || value > 4 || (value >= 3 && index != 6))
-            return fail(PP_ERR_INVALID, "tile kernel: k in 4..6, value 0..2 (3, 4: k = 6 only)");
+            return fail(PP_ERR_INVALID, "tile kernel: k in 4..6, value 0..4 (3, 4: k = 6 only)");
         pp::set_tile_kernel_variant(index, value);
         return PP_OK;
     }

@@ -39,6 +39,16 @@ __device__ __forceinline__ int sw(int i) { return i ^ (((i >> 4) & 3) * 5); }
 // 5p ^ 5q for disjoint two-bit p, q.  Slot offsets of an op's letters are
 // the same for every lane, so each address costs one XOR with a uniform.
 
+// Workgroup barrier for LDS data: the fences are scoped to LDS, so global
+// loads still in flight (a prefetched next tile) are not waited for, which a
+// full __syncthreads() would do.  Every barrier in this file orders LDS
+// accesses only (threads never exchange data through global memory).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 __device__ __forceinline__ double lds_ld(const T *p, int i) { return (double)p[sw(i)]; }
 template <typename T>
@@ -72,9 +82,9 @@ template <int BLOCK>
 __device__ double block_sum_d(double v, double *red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     const int w = threadIdx.x >> 6;
-    __syncthreads();
+    lds_barrier();
     if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
+    lds_barrier();
     double tot = 0.0;
     for (int i = 0; i < BLOCK / 64; ++i) tot += red[i];
     return tot;
@@ -84,9 +94,9 @@ template <int BLOCK>
 __device__ long long block_sum_i(long long v, long long *red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     const int w = threadIdx.x >> 6;
-    __syncthreads();
+    lds_barrier();
     if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
+    lds_barrier();
     long long tot = 0;
     for (int i = 0; i < BLOCK / 64; ++i) tot += red[i];
     return tot;
@@ -109,12 +119,15 @@ __device__ __forceinline__ int u1_apply(T *lc, uint8_t *lp, int a, const double 
     const double m20 = M[6], m21 = M[7], m22 = M[8];
     if (NQ < BLOCK && tid >= NQ) return 0;
     const int oX = sw(1 << sh), oZ = sw(2 << sh), oY = sw(3 << sh);
+    // inserting the zero digit and sw are both linear and tid, j * BLOCK
+    // have disjoint bits: one per-thread word, the rest uniform
+    const int tbase = sw(((tid & ~lowmask) << 2) | (tid & lowmask));
     int iX[QPT], iY[QPT], iZ[QPT];
     double cx[QPT], cy[QPT], cz[QPT];
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
-        const int u = tid + j * BLOCK;
-        const int sbase = sw(((u & ~lowmask) << 2) | (u & lowmask));
+        const int uj = j * BLOCK;
+        const int sbase = tbase ^ sw(((uj & ~lowmask) << 2) | (uj & lowmask));
         iX[j] = sbase ^ oX;
         iZ[j] = sbase ^ oZ;
         iY[j] = sbase ^ oY;
@@ -367,7 +380,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
     int cb = o0;
     while (cb < o1) {
         const int cn = (o1 - cb) < OPCH ? (o1 - cb) : OPCH;
-        __syncthreads();
+        lds_barrier();
         if (!preloaded && tid < cn) {
             const DOp op = ops[cb + tid];
             oc->ops[tid] = op;
@@ -377,7 +390,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
                 for (int j = 0; j < 9; ++j) oc->maps[tid][j] = src[j];
             }
         }
-        __syncthreads();
+        lds_barrier();
         preloaded = false;
         int i = 0;
         while (i < cn) {
@@ -406,7 +419,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
                 if (TRACK) updates += tcount * ngates;
                 ++i;
             }
-            __syncthreads();
+            lds_barrier();
         }
         cb += i;
     }
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((N >= 7 &
         lc[i] = (T)0;
         if (TRACK) lp[i] = 0;
     }
-    __syncthreads();
+    lds_barrier();
     if (d.coef_in) {
         const T *in = reinterpret_cast<const T *>(d.coef_in);
         for (int i = tid; i < size; i += BLOCK) lc[sw(i)] = in[i];
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((N >= 7 &
             if (TRACK) lp[sw(s)] = 1;
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     long long tcount = 0, updates = 0;
     if (TRACK) {
@@ -516,12 +529,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((BLOCK ==
     const long long toff = base | deposit_digits(tid, d.qubits, 0, k);
 
     T *g = reinterpret_cast<T *>(d.coef);
+    const int stid = sw(tid);  // sw(tid + r * BLOCK) = sw(tid) ^ sw(r * BLOCK)
     for (int i = tid, r = 0; i < size; i += BLOCK, ++r) {
         const long long gi = toff | deposit_digits(r * BLOCK, d.qubits, 0, k);
-        lc[sw(i)] = g[gi];
-        if (TRACK) lp[sw(i)] = d.pres[gi];
+        const int li = stid ^ sw(r * BLOCK);
+        lc[li] = g[gi];
+        if (TRACK) lp[li] = d.pres[gi];
     }
-    __syncthreads();
+    lds_barrier();
 
     long long tcount = 0, updates = 0;
     if (TRACK) {
@@ -533,133 +548,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((BLOCK ==
 
     for (int i = tid, r = 0; i < size; i += BLOCK, ++r) {
         const long long gi = toff | deposit_digits(r * BLOCK, d.qubits, 0, k);
-        g[gi] = lc[sw(i)];
-        if (TRACK) d.pres[gi] = lp[sw(i)];
+        const int li = stid ^ sw(r * BLOCK);
+        g[gi] = lc[li];
+        if (TRACK) d.pres[gi] = lp[li];
     }
     if (TRACK && tid == 0 && updates) atomicAdd(d.counters, (unsigned long long)updates);
 }
-
-// ------------------------------------------------- streaming tile kernel
-// Persistent form of tile_kernel for untracked runs: a co-resident grid
-// walks the launch's tiles with stride gridDim.x, and every workgroup issues
-// the global loads of its next tile into registers before it runs the ops of
-// the current one, so HBM latency overlaps the LDS work.
-struct TileLoc {
-    const TilePassDesc *d;
-    long long toff;
-};
-
-template <int K>
-__device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ descs, const TileGroups &grp, int b,
-                                               int tid) {
-    int g = 0;
-    while (g + 1 < grp.ngroups && b >= grp.first_block[g + 1]) ++g;
-    const int rel = b - grp.first_block[g];
-    const TilePassDesc *d = descs + grp.first_desc[g] + (rel >> grp.shift[g]);
-    const long long tile = rel & ((1 << grp.shift[g]) - 1);
-    const uint64_t qubits = d->qubits;
-    const int n = d->n;
-    unsigned inmask = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        if (j < K) inmask |= 1u << (unsigned)((qubits >> (8 * j)) & 0xff);
-    long long base = 0, t = tile;
-    for (int q = 0; q < n; ++q) {
-        if ((inmask >> q) & 1u) continue;
-        base |= (t & 3ll) << (2 * q);
-        t >>= 2;
-    }
-    return TileLoc{d, base | deposit_digits(tid, qubits, 0, 4)};
-}
-
-template <typename T, int K>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void tile_stream_kernel(
-    const TilePassDesc *__restrict__ descs, TileGroups grp) {
-    constexpr int BLOCK = 256;
-    constexpr int size = 1 << (2 * K);
-    constexpr int PER = size / BLOCK;
-    static_assert(K >= 4, "the thread index supplies four digits");
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ long long redi[BLOCK / 64];
-    __shared__ OpCache oc;
-    T *lc = reinterpret_cast<T *>(smem);
-    const int tid = threadIdx.x;
-    const int total = grp.first_block[grp.ngroups];
-    int blk = blockIdx.x;
-    if (blk >= total) return;
-    TileLoc cur = locate_tile<K>(descs, grp, blk, tid);
-    T pre[PER];
-    {
-        const T *g = reinterpret_cast<const T *>(cur.d->coef);
-        const uint64_t qubits = cur.d->qubits;
-#pragma unroll
-        for (int r = 0; r < PER; ++r) pre[r] = g[cur.toff | deposit_digits(r << 8, qubits, 4, K)];
-    }
-    long long tcount = 0, updates = 0;
-    for (;;) {
-        __syncthreads();  // the previous tile's LDS reads are done
-#pragma unroll
-        for (int r = 0; r < PER; ++r) lc[sw(tid + r * BLOCK)] = pre[r];
-        const int o0 = cur.d->op_begin, o1 = cur.d->op_end;
-        const int cn = (o1 - o0) < OPCH ? (o1 - o0) : OPCH;
-        // first op chunk of this tile, then the next tile's prefetch
-        DOp opr{};
-        double mr[9];
-        if (tid < cn) {
-            opr = cur.d->ops[o0 + tid];
-            if (opr.kind == DOP_U1) {
-                const double *src = cur.d->maps + 9ull * opr.map;
-#pragma unroll
-                for (int j = 0; j < 9; ++j) mr[j] = src[j];
-            }
-        }
-        const int nblk = blk + gridDim.x;
-        const bool has_next = nblk < total;
-        TileLoc nxt = cur;
-        if (has_next) {
-            nxt = locate_tile<K>(descs, grp, nblk, tid);
-            const T *g = reinterpret_cast<const T *>(nxt.d->coef);
-            const uint64_t qubits = nxt.d->qubits;
-#pragma unroll
-            for (int r = 0; r < PER; ++r) pre[r] = g[nxt.toff | deposit_digits(r << 8, qubits, 4, K)];
-        }
-        if (tid < cn) {
-            oc.ops[tid] = opr;
-            if (opr.kind == DOP_U1) {
-#pragma unroll
-                for (int j = 0; j < 9; ++j) oc.maps[tid][j] = mr[j];
-            }
-        }
-        run_ops<T, false, K, BLOCK>(lc, nullptr, cur.d->ops, cur.d->maps, o0, o1, tcount, updates, redi, &oc, true);
-        {
-            T *g = reinterpret_cast<T *>(cur.d->coef);
-            const uint64_t qubits = cur.d->qubits;
-#pragma unroll
-            for (int r = 0; r < PER; ++r) g[cur.toff | deposit_digits(r << 8, qubits, 4, K)] = lc[sw(tid + r * BLOCK)];
-        }
-        if (!has_next) break;
-        blk = nblk;
-        cur = nxt;
-    }
-}
-
-// --------------------------------------------------- register tile kernel
-// One wave per 4^6-slot tile, the tile held in registers as FP64: lane l and
-// register e hold the slot whose local digits are the lane digits
-// (l0, l1, l2) = (l & 3, (l >> 2) & 3, l >> 4) and the register digits
-// (t0, t1, t2) = (e & 3, (e >> 2) & 3, e >> 4) of the current layout
-// (t0 < t1 < t2, l0 < l1 < l2 the other three).  The ops of a SEG segment act
-// on its register digits only, so a U1 is 16 register quads times a 3x3 map
-// and a CX is a fixed set of register moves; between segments the tile is
-// re-laid through LDS.  A layout whose register digits avoid local digits 0
-// and 1 has lanes 0-15 on 16 consecutive slots (128 bytes) and is loaded from
-// and stored to HBM directly.  Ops run in list order with the same FP64
-// expressions as the LDS kernels; FP32 weights are rounded where those
-// kernels store to LDS (after every op outside a GROUP and at the end of each
-// GROUP), so every launch shape gives bit-identical weights.
-struct RegLayout {
-    int t0, t1, t2, l0, l1, l2;
-};
 
 // Weights are read and written with buffer instructions: one resource per
 // tile (base = the tile's first slot), the lane's slot offset in a VGPR and
@@ -689,6 +583,140 @@ struct BufIO<float> {
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
     }
+};
+
+// ------------------------------------------------- streaming tile kernel
+// Persistent form of tile_kernel for untracked runs: a co-resident grid
+// walks the launch's tiles with stride gridDim.x, and every workgroup issues
+// the global loads of its next tile into registers before it runs the ops of
+// the current one, so HBM latency overlaps the LDS work (the barriers in
+// run_ops are LDS-scoped and do not wait for those loads).  Weights move
+// with buffer instructions: the tile base is uniform, the thread's slot
+// offset (digits 0-3) is one VGPR and the register's offset (digits 4 and
+// up) is uniform, so the prefetch costs no address registers; the launcher
+// takes this kernel only for n <= 14, where both offsets fit 31 bits.
+struct TileLoc {
+    const TilePassDesc *d;
+    long long base;
+    unsigned voff;  // bytes
+};
+
+template <typename T, int K>
+__device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ descs, const TileGroups &grp, int b,
+                                               int tid) {
+    int g = 0;
+    while (g + 1 < grp.ngroups && b >= grp.first_block[g + 1]) ++g;
+    const int rel = b - grp.first_block[g];
+    const TilePassDesc *d = descs + grp.first_desc[g] + (rel >> grp.shift[g]);
+    const long long tile = rel & ((1 << grp.shift[g]) - 1);
+    const uint64_t qubits = d->qubits;
+    const int n = d->n;
+    unsigned inmask = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < K) inmask |= 1u << (unsigned)((qubits >> (8 * j)) & 0xff);
+    long long base = 0, t = tile;
+    for (int q = 0; q < n; ++q) {
+        if ((inmask >> q) & 1u) continue;
+        base |= (t & 3ll) << (2 * q);
+        t >>= 2;
+    }
+    return TileLoc{d, base, (unsigned)deposit_digits(tid, qubits, 0, 4) * (unsigned)sizeof(T)};
+}
+
+template <typename T, int K>
+__device__ __forceinline__ unsigned stream_soff(uint64_t qubits, int r) {
+    return (unsigned)deposit_digits(r << 8, qubits, 4, K) * (unsigned)sizeof(T);
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void tile_stream_kernel(
+    const TilePassDesc *__restrict__ descs, TileGroups grp) {
+    constexpr int BLOCK = 256;
+    constexpr int size = 1 << (2 * K);
+    constexpr int PER = size / BLOCK;
+    static_assert(K >= 4, "the thread index supplies four digits");
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long redi[BLOCK / 64];
+    __shared__ OpCache oc;
+    T *lc = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x;
+    const int stid = sw(tid);
+    const int total = grp.first_block[grp.ngroups];
+    int blk = blockIdx.x;
+    if (blk >= total) return;
+    TileLoc cur = locate_tile<T, K>(descs, grp, blk, tid);
+    T pre[PER];
+    {
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(cur.d->coef) + cur.base);
+        const uint64_t qubits = cur.d->qubits;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, cur.voff, stream_soff<T, K>(qubits, r));
+    }
+    long long tcount = 0, updates = 0;
+    for (;;) {
+        lds_barrier();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
+        const int o0 = cur.d->op_begin, o1 = cur.d->op_end;
+        const int cn = (o1 - o0) < OPCH ? (o1 - o0) : OPCH;
+        // first op chunk of this tile, then the next tile's prefetch
+        DOp opr{};
+        double mr[9];
+        if (tid < cn) {
+            opr = cur.d->ops[o0 + tid];
+            if (opr.kind == DOP_U1) {
+                const double *src = cur.d->maps + 9ull * opr.map;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) mr[j] = src[j];
+            }
+        }
+        const int nblk = blk + gridDim.x;
+        const bool has_next = nblk < total;
+        TileLoc nxt = cur;
+        if (has_next) {
+            nxt = locate_tile<T, K>(descs, grp, nblk, tid);
+            const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
+            const uint64_t qubits = nxt.d->qubits;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K>(qubits, r));
+        }
+        if (tid < cn) {
+            oc.ops[tid] = opr;
+            if (opr.kind == DOP_U1) {
+#pragma unroll
+                for (int j = 0; j < 9; ++j) oc.maps[tid][j] = mr[j];
+            }
+        }
+        run_ops<T, false, K, BLOCK>(lc, nullptr, cur.d->ops, cur.d->maps, o0, o1, tcount, updates, redi, &oc, true);
+        {
+            const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(cur.d->coef) + cur.base);
+            const uint64_t qubits = cur.d->qubits;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) BufIO<T>::st(rs, cur.voff, stream_soff<T, K>(qubits, r), lc[stid ^ sw(r * BLOCK)]);
+        }
+        if (!has_next) break;
+        blk = nblk;
+        cur = nxt;
+    }
+}
+
+// --------------------------------------------------- register tile kernel
+// One wave per 4^6-slot tile, the tile held in registers as FP64: lane l and
+// register e hold the slot whose local digits are the lane digits
+// (l0, l1, l2) = (l & 3, (l >> 2) & 3, l >> 4) and the register digits
+// (t0, t1, t2) = (e & 3, (e >> 2) & 3, e >> 4) of the current layout
+// (t0 < t1 < t2, l0 < l1 < l2 the other three).  The ops of a SEG segment act
+// on its register digits only, so a U1 is 16 register quads times a 3x3 map
+// and a CX is a fixed set of register moves; between segments the tile is
+// re-laid through LDS.  A layout whose register digits avoid local digits 0
+// and 1 has lanes 0-15 on 16 consecutive slots (128 bytes) and is loaded from
+// and stored to HBM directly.  Ops run in list order with the same FP64
+// expressions as the LDS kernels; FP32 weights are rounded where those
+// kernels store to LDS (after every op outside a GROUP and at the end of each
+// GROUP), so every launch shape gives bit-identical weights.
+struct RegLayout {
+    int t0, t1, t2, l0, l1, l2;
 };
 
 __device__ __forceinline__ RegLayout reg_layout(unsigned triple) {
@@ -757,7 +785,7 @@ __device__ __forceinline__ void reg_relayout(double (&v)[64], T *lds, const RegL
 #pragma unroll
         for (int e = 0; e < 64; ++e) *reinterpret_cast<T *>(base + (lw ^ reg_word(rb, e))) = (T)v[e];
     }
-    __syncthreads();
+    lds_barrier();
     {
         const int lw = reg_lane_word(B, lane) << S;
         RegBasis rb = reg_basis(B);
@@ -766,7 +794,7 @@ __device__ __forceinline__ void reg_relayout(double (&v)[64], T *lds, const RegL
 #pragma unroll
         for (int e = 0; e < 64; ++e) v[e] = (double)*reinterpret_cast<const T *>(base + (lw ^ reg_word(rb, e)));
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // Global slot offsets of a layout (lanes 0-15 must be local digits 0 and 1).
@@ -1095,7 +1123,7 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const GradPassDesc *__restr
     }
     for (int cb = d.op_begin; cb < d.op_end; cb += OPCH) {
         const int cn = (d.op_end - cb) < OPCH ? (d.op_end - cb) : OPCH;
-        __syncthreads();
+        lds_barrier();
         if (tid < cn) {
             const DOp op = d.ops[cb + tid];
             oc.ops[tid] = op;
@@ -1105,7 +1133,7 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const GradPassDesc *__restr
                 for (int j = 0; j < 9; ++j) oc.maps[tid][j] = src[j];
             }
         }
-        __syncthreads();
+        lds_barrier();
         for (int i = 0; i < cn; ++i) {
             const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc.ops[i])[0]);
             const uint32_t slot = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc.ops[i])[3]);
@@ -1114,7 +1142,7 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const GradPassDesc *__restr
                 if (b >= 3) {
                     const double part = block_sum_d<BLOCK>(join_part<K, BLOCK>(lc, lr, a, b, tid), redd);
                     if (tid == 0) d.partials[(long long)(slot - d.slot_base) * d.ntiles + tile] = part;
-                    __syncthreads();
+                    lds_barrier();
                 }
                 const double *M = oc.maps[i];
                 const double Mt[9] = {M[0], M[3], M[6], M[1], M[4], M[7], M[2], M[5], M[8]};
@@ -1126,10 +1154,10 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const GradPassDesc *__restr
                     cx_apply<double, false, K, BLOCK>(lr, nullptr, a, b, tid);
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
-    __syncthreads();
+    lds_barrier();
     for (int i = tid; i < size; i += BLOCK) {
         const long long gi = base | deposit_digits(i, d.qubits, 0, K);
         d.c[gi] = lc[sw(i)];
@@ -1289,14 +1317,14 @@ __global__ __launch_bounds__(256) void compact_write_kernel(const T *coef, const
     const long long b0 = (long long)blockIdx.x * CMP_CHUNK;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x == 0) running = offsets[blockIdx.x];
-    __syncthreads();
+    lds_barrier();
     for (int r = 0; r < CMP_CHUNK; r += 256) {
         const long long i = b0 + r + threadIdx.x;
         const bool p = i < size && slot_kept(coef, pres, i);
         const unsigned long long bal = __ballot(p);
         const int below = __popcll(bal & ((1ull << lane) - 1ull));
         if (lane == 0) wcount[w] = __popcll(bal);
-        __syncthreads();
+        lds_barrier();
         int off = running;
         for (int v = 0; v < w; ++v) off += wcount[v];
         if (p) {
@@ -1310,9 +1338,9 @@ __global__ __launch_bounds__(256) void compact_write_kernel(const T *coef, const
             zo[pos] = z;
             co[pos] = (double)coef[i];
         }
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x == 0) running += wcount[0] + wcount[1] + wcount[2] + wcount[3];
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -1393,8 +1421,9 @@ hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int d
                  : launch_res_b<float, false>(d_descs, ndescs, n, lds, s);
 }
 
-// defaults measured by the autotuner on MI355X: one wave per 4^5-slot tile
-static int g_tile_variant[8] = {0, 0, 0, 0, 0, 2, 0, 0};
+// defaults measured on MI355X: one wave per 4^5-slot tile; persistent
+// prefetching workgroups for 4^6-slot tiles
+static int g_tile_variant[8] = {0, 0, 0, 0, 0, 2, 1, 0};
 void set_tile_kernel_variant(int k, int variant) {
     if (k >= 0 && k < 8) g_tile_variant[k] = variant;
 }
@@ -1447,19 +1476,19 @@ static hipError_t launch_tile_t(const TilePassDesc *d, const TileGroups &grp, si
         hipLaunchKernelGGL(fn, dim3(nblocks), dim3(64), lds, s, d, grp);
         return hipGetLastError();
     }
-    if (!TRACK && K <= 6 && g_tile_variant[K] == 1) {
+    if (!TRACK && K <= 6 && g_tile_variant[K] == 1 && max_n <= 14) {
         auto fn = tile_stream_kernel<T, (K <= 6 ? K : 6)>;
-        static int resident_blocks = 0;
-        if (!resident_blocks) {
+        static int rb = 0;
+        if (!rb) {
             hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                max_lds_bytes() - (int)kStaticLdsReserve);
             if (e != hipSuccess) return e;
             int per_cu = 0;
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256, lds);
             if (e != hipSuccess) return e;
-            resident_blocks = std::max(per_cu, 1) * num_cus();
+            rb = std::max(per_cu, 1) * num_cus();
         }
-        const int grid = nblocks < resident_blocks ? nblocks : resident_blocks;
+        const int grid = nblocks < rb ? nblocks : rb;
         hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, s, d, grp);
         return hipGetLastError();
     }
