@@ -148,13 +148,17 @@ def timed_steps(fn, steps, torch):
     return time.perf_counter() - t0, np.array(lat)
 
 
-def measured_traffic(workload, dtype):
+TILE_KERNEL_NAMES = {0: "tile_kernel", 1: "tile_stream_kernel", 2: "tile_kernel", 3: "tile_reg_kernel",
+                     4: "tile_reg_kernel"}
+
+
+def measured_traffic(kernel, workload, dtype):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE/WRITE_SIZE summary (already scaled by the copy-kernel
-    calibration), or None when no summary covers this workload or the kernel
-    source changed since the counters were taken."""
+    calibration), or None when no summary covers this kernel and workload or
+    the kernel source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if dtype != "f64" or not os.path.exists(path):
         return None
     rec = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
@@ -293,9 +297,10 @@ def main():
     if dname == "tile_pass" and dlaunch:
         alg_bytes = bytes_step * args.steps
         achieved = alg_bytes / (dms * 1e-3) / 1e9
-        roof = {"kernel": "tile_kernel", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+        kname = TILE_KERNEL_NAMES.get(L.tune_get(L.PP_TUNE_TILE_KERNEL, 6), "tile_kernel")
+        roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                "traffic": measured_traffic(args.workload, args.dtype),
+                "traffic": measured_traffic(kname, args.workload, args.dtype),
                 "launches": dlaunch, "avg_launch_us": dms * 1e3 / dlaunch,
                 "alg_bytes_per_launch": alg_bytes / dlaunch}
     else:
