@@ -194,8 +194,9 @@ typedef struct pp_server pp_server;
  * mem_budget_bytes.  Admitted requests share work: every loop iteration
  * issues one batched tile pass holding the next pass of every active tiled
  * request (requests join and leave between iterations), while circuits that
- * fit one workgroup's LDS run whole on a second stream, overlapping the
- * passes.  Each request's result is bit-identical to its own pp_evaluate. */
+ * fit one workgroup's LDS run whole beside the passes: the pending ones are
+ * launched together (one workgroup each) on whichever of three side streams
+ * is idle.  Each request's result is bit-identical to its own pp_evaluate. */
 PP_API pp_status pp_server_create(int64_t mem_budget_bytes, int32_t max_active, pp_server **out);
 
 /* Queues an evaluation of circuit c (gates, theta and observable set) and

@@ -1348,12 +1348,17 @@ struct ServedReq {
     double t_submit = 0, t_done = 0;
     size_t pass = 0;
     int slot = -1;
+    bool resident = false;  // runs whole in one LDS-resident launch
     hipEvent_t ev = nullptr;
     double result = 0;
     pp_status status = PP_OK;
 };
 
 constexpr int kRing = 4;
+// LDS-resident requests run whole, batched per launch, on a few streams of
+// their own beside the tile passes (kernels of one stream run in order, so a
+// single side stream would serialize one-workgroup launches)
+constexpr int kSideLanes = 3;
 
 }  // namespace
 
@@ -1378,7 +1383,15 @@ struct pp_server {
         bool used = false;
     } ring[kRing];
     int ring_i = 0;
-    int64_t iterations = 0, tile_launches = 0, max_in_flight = 0;
+    struct SideLane {
+        hipStream_t st = nullptr;
+        void *d = nullptr, *h = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool busy = false;
+    } lane[kSideLanes];
+    std::vector<ServedReq *> res_pending;
+    int64_t iterations = 0, tile_launches = 0, max_in_flight = 0, resident_launches = 0;
     int dev = 0;
 };
 
@@ -1425,7 +1438,11 @@ pp_status start_request(pp_server *S, ServedReq *r) {
     fill_plan_stats(c);
     r->prepared = true;
     double *out = S->d_results + r->slot;
-    if (c->engine != PP_ENGINE_DENSE || c->track || c->dplan.resident) {
+    if (c->engine == PP_ENGINE_DENSE && !c->track && c->dplan.resident) {
+        r->resident = true;  // launched with the other pending resident requests
+        return PP_OK;
+    }
+    if (c->engine != PP_ENGINE_DENSE || c->track) {
         st = pp_evaluate(c, S->side, out);
         if (st != PP_OK) return st;
         return finish_async(S, r, S->side);
@@ -1434,6 +1451,71 @@ pp_status start_request(pp_server *S, ServedReq *r) {
     HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(),
                                  S->main));
     r->pass = 0;
+    return PP_OK;
+}
+
+// Launches every pending resident request on an idle side lane: the maps of
+// all of them in one compose launch, then one resident launch per (dtype, n)
+// with one workgroup per request.  Returns false when every lane is busy.
+pp_status launch_resident_batch(pp_server *S, bool *launched) {
+    *launched = false;
+    pp_server::SideLane *Ln = nullptr;
+    for (auto &cand : S->lane) {
+        if (cand.busy && hipEventQuery(cand.ev) == hipSuccess) cand.busy = false;
+        if (!cand.busy) {
+            Ln = &cand;
+            break;
+        }
+    }
+    if (!Ln) return PP_OK;
+    std::vector<ServedReq *> &P = S->res_pending;
+    std::stable_sort(P.begin(), P.end(), [](ServedReq *a, ServedReq *b) {
+        return a->c->dbytes != b->c->dbytes ? a->c->dbytes > b->c->dbytes : a->c->n > b->c->n;
+    });
+    std::vector<pp::ComposeDesc> comp;
+    for (ServedReq *r : P)
+        if (r->c->dplan.nmaps() > 0) comp.push_back(r->c->h_comp);
+    std::vector<pp::ResidentDesc> rd;
+    for (ServedReq *r : P) {
+        pp::ResidentDesc d = r->c->h_res;
+        d.expval_out = S->d_results + r->slot;
+        rd.push_back(d);
+    }
+    const size_t cbytes = comp.size() * sizeof(pp::ComposeDesc);
+    const size_t roff = (cbytes + 255) & ~(size_t)255;
+    const size_t bytes = roff + rd.size() * sizeof(pp::ResidentDesc);
+    if (bytes > Ln->cap) {  // the lane is idle: its buffers are free
+        if (Ln->d) (void)hipFree(Ln->d);
+        if (Ln->h) (void)hipHostFree(Ln->h);
+        Ln->d = Ln->h = nullptr;
+        Ln->cap = 0;
+        const size_t cap = std::max<size_t>(2 * bytes, 1 << 16);
+        HIPCHK(hipMalloc(&Ln->d, cap));
+        HIPCHK(hipHostMalloc(&Ln->h, cap, hipHostMallocDefault));
+        Ln->cap = cap;
+    }
+    if (!comp.empty()) std::memcpy(Ln->h, comp.data(), cbytes);
+    std::memcpy((unsigned char *)Ln->h + roff, rd.data(), rd.size() * sizeof(pp::ResidentDesc));
+    HIPCHK(hipMemcpyAsync(Ln->d, Ln->h, bytes, hipMemcpyHostToDevice, Ln->st));
+    if (!comp.empty()) HIPCHK(pp::launch_compose((const pp::ComposeDesc *)Ln->d, (int)comp.size(), Ln->st));
+    const pp::ResidentDesc *dres = (const pp::ResidentDesc *)((unsigned char *)Ln->d + roff);
+    size_t i = 0;
+    while (i < P.size()) {
+        size_t j = i;
+        while (j < P.size() && P[j]->c->n == P[i]->c->n && P[j]->c->dbytes == P[i]->c->dbytes) ++j;
+        HIPCHK(pp::launch_resident(dres + i, (int)(j - i), P[i]->c->n, P[i]->c->dbytes, false, Ln->st));
+        S->resident_launches++;
+        i = j;
+    }
+    for (ServedReq *r : P) {
+        pp_status st = finish_async(S, r, Ln->st);
+        if (st != PP_OK) return st;
+    }
+    if (!Ln->ev) HIPCHK(hipEventCreateWithFlags(&Ln->ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(Ln->ev, Ln->st));
+    Ln->busy = true;
+    P.clear();
+    *launched = true;
     return PP_OK;
 }
 
@@ -1478,13 +1560,26 @@ void server_loop(pp_server *S) {
                 (void)hipStreamSynchronize(S->main);
                 std::lock_guard<std::mutex> lk(S->mu);
                 complete(S, r, st);
+            } else if (r->resident) {
+                S->res_pending.push_back(r);
+            }
+        }
+        if (!S->res_pending.empty()) {
+            bool res_launched = false;
+            std::vector<ServedReq *> batch = S->res_pending;
+            pp_status st = launch_resident_batch(S, &res_launched);
+            if (st != PP_OK) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (ServedReq *r : batch)
+                    if (r->state == 1) complete(S, r, st);
+                S->res_pending.clear();
             }
         }
         // one iteration: the next pass of every active tiled request, one
         // launch per tile size
         std::vector<ServedReq *> tiled;
         for (ServedReq *r : S->active)
-            if (r->state == 1 && r->prepared) tiled.push_back(r);
+            if (r->state == 1 && r->prepared && !r->resident) tiled.push_back(r);
         bool launched = false;
         for (int k = 4; k <= 7 && !tiled.empty(); ++k) {
             std::vector<ServedReq *> grp;
@@ -1594,11 +1689,15 @@ extern "C" pp_status pp_server_create(int64_t mem_budget_bytes, int32_t max_acti
     hipError_t e = hipGetDevice(&S->dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->main, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking);
+    for (auto &Ln : S->lane)
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&Ln.st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc((void **)&S->d_results, sizeof(double) * max_active);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_results, sizeof(double) * max_active, hipHostMallocDefault);
     if (e != hipSuccess) {
         if (S->main) (void)hipStreamDestroy(S->main);
         if (S->side) (void)hipStreamDestroy(S->side);
+        for (auto &Ln : S->lane)
+            if (Ln.st) (void)hipStreamDestroy(Ln.st);
         if (S->d_results) (void)hipFree(S->d_results);
         delete S;
         return fail(PP_ERR_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
@@ -1677,6 +1776,7 @@ extern "C" void pp_server_destroy(pp_server *S) {
     if (S->th.joinable()) S->th.join();
     (void)hipStreamSynchronize(S->main);
     (void)hipStreamSynchronize(S->side);
+    for (auto &Ln : S->lane) (void)hipStreamSynchronize(Ln.st);
     for (auto &kv : S->reqs) {
         if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
         delete kv.second;
@@ -1688,6 +1788,12 @@ extern "C" void pp_server_destroy(pp_server *S) {
     }
     (void)hipFree(S->d_results);
     (void)hipHostFree(S->h_results);
+    for (auto &Ln : S->lane) {
+        if (Ln.ev) (void)hipEventDestroy(Ln.ev);
+        if (Ln.d) (void)hipFree(Ln.d);
+        if (Ln.h) (void)hipHostFree(Ln.h);
+        (void)hipStreamDestroy(Ln.st);
+    }
     (void)hipStreamDestroy(S->main);
     (void)hipStreamDestroy(S->side);
     delete S;
