@@ -180,6 +180,47 @@ def dense_bytes(objs):
     return total
 
 
+def gradient_leg(api, torch):
+    """n = 8, HEA-40, TFIM (960 parameters): the adjoint gradient (checkpoint
+    every 5 layers) against the parameter-shift gradient, whose 1,920 shifted
+    evaluations run as one parameter sweep."""
+    from paper_2502_10685_amd import workloads as W
+    wc = W.config4()
+    c = api.Circuit.from_workload(wc)
+    ev, g_adj = c.gradient(5 * 32)
+    g_psr = c.psr_gradient(wc.theta).numpy()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c.gradient(5 * 32)
+    torch.cuda.synchronize()
+    t_adj = (time.perf_counter() - t0) / reps
+    pc, rot = c._psr
+    base = wc.theta[wc.param[rot]]
+    th = np.repeat(base[None, :], 2 * rot.size, axis=0)
+    for j in range(rot.size):
+        th[2 * j, j] += math.pi / 2
+        th[2 * j + 1, j] -= math.pi / 2
+    th_dev = torch.tensor(th, device="cuda")
+    out = torch.empty(th.shape[0], dtype=torch.float64, device="cuda")
+    pc.evaluate_thetas(th_dev, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pc.evaluate_thetas(th_dev, out=out)
+    torch.cuda.synchronize()
+    t_psr = (time.perf_counter() - t0) / reps
+    u_eval = int(count_updates(api, [wc], "f64")[0][0])
+    c.close()
+    return {"workload": "n=8 HEA-40 (1280 gates, 960 theta), TFIM, FP64",
+            "adjoint_ms": t_adj * 1e3, "psr_sweep_ms": t_psr * 1e3, "psr_evaluations": int(th.shape[0]),
+            "psr_evaluations_per_s": th.shape[0] / t_psr,
+            "psr_updates_per_s": th.shape[0] * u_eval / t_psr,
+            "adjoint_speedup_vs_psr": t_psr / t_adj,
+            "max_abs_adjoint_minus_psr": float(np.max(np.abs(g_adj.cpu().numpy() - g_psr)))}
+
+
 def cpu_baseline(circs, gpu_vals, seconds, updates):
     """The oracle's scalar propagator on a bounded sample of the workload: every
     8th circuit whose estimated cost still fits the time budget."""
@@ -223,6 +264,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
                     help="time the tuning candidates on this device first (defaults are MI355X measurements)")
@@ -359,6 +401,12 @@ def main():
             log(f"serving lambda={lam:.0f}: p50 {sv['latency_ms']['p50']:.1f} ms, p99 "
                 f"{sv['latency_ms']['p99']:.1f} ms, {sv['updates_per_s']:.3e} updates/s")
             res["serving"].append(sv)
+
+    if not args.no_grad and args.workload == "batch512":
+        log("gradient: adjoint vs parameter-shift sweep")
+        res["gradient"] = gradient_leg(api, torch)
+        log(f"gradient: adjoint {res['gradient']['adjoint_ms']:.2f} ms, psr sweep "
+            f"{res['gradient']['psr_sweep_ms']:.2f} ms")
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

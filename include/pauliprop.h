@@ -161,6 +161,20 @@ PP_API pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval);
  * Each circuit's result is bit-identical to its own pp_evaluate. */
 PP_API pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, void *stream, double *d_expvals);
 
+/* Parameter sweep (the parameter-shift variants of a training step, a scan
+ * over theta): enqueues <O> of circuit c at `count` parameter vectors.
+ * thetas: count x n_params doubles, row-major, host memory (on_device = 0,
+ * copied before return) or device memory (on_device = 1, read on `stream`).
+ * d_expvals: caller-owned device array of `count` doubles.  All sets share
+ * the schedule: each tile pass of all of them is one launch (LDS-resident
+ * circuits: one launch), with per-set maps and 4^n weights that the circuit
+ * keeps between calls (count x 4^n x sizeof(weight) bytes of device memory;
+ * PP_ERR_NOMEM when that does not fit).  Each result is bit-identical to
+ * pp_evaluate with the same theta.  DENSE engine without term tracking only
+ * (else PP_ERR_STATE); theta set with pp_circuit_set_theta is not used. */
+PP_API pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const double *thetas, int32_t on_device,
+                                    void *stream, double *d_expvals);
+
 /* Enqueues <O> and its gradient with respect to theta (adjoint method on the
  * DENSE engine): d_expval one double, d_grad n_params doubles (caller-owned
  * device memory; contributions of gates sharing a parameter are summed).

@@ -66,6 +66,8 @@ class Circuit:
         q0 = np.ascontiguousarray(q0, dtype=np.int32)
         q1 = np.ascontiguousarray(q1, dtype=np.int32)
         param = np.ascontiguousarray(param, dtype=np.int32)
+        self._op, self._q0, self._q1, self._param = op, q0, q1, param
+        self._psr = None
         self.m = int(op.shape[0])
         L.check(self._lib.pp_circuit_load_gates(self._h, self.m, _ptr(op), _ptr(q0), _ptr(q1),
                                                 _ptr(param), int(n_params)))
@@ -75,6 +77,8 @@ class Circuit:
         x = np.ascontiguousarray(x, dtype=np.uint64)
         z = np.ascontiguousarray(z, dtype=np.uint64)
         c = np.ascontiguousarray(c, dtype=np.float64)
+        self._obs = (x, z, c)
+        self._psr = None
         L.check(self._lib.pp_circuit_set_observable(self._h, int(x.shape[0]), _ptr(x), _ptr(z), _ptr(c)))
 
     def set_theta(self, theta, stream=None):
@@ -98,6 +102,57 @@ class Circuit:
             out = torch.empty((), dtype=torch.float64, device="cuda")
         L.check(self._lib.pp_evaluate(self._h, _stream(stream), ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def evaluate_thetas(self, thetas, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """<O> at every row of thetas (count x n_params), one set of shared
+        launches; a CUDA tensor is read in place, anything else is copied."""
+        if isinstance(thetas, torch.Tensor) and thetas.is_cuda:
+            t = thetas.detach().to(torch.float64).contiguous()
+            count = int(t.shape[0]) if t.dim() > 1 else 1
+            ptr, on_dev = ctypes.c_void_p(t.data_ptr()), 1
+            keep = t
+        else:
+            t = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64))
+            count = int(t.shape[0]) if t.ndim > 1 else 1
+            if t.size == 0:
+                t = np.zeros(max(count, 1))
+            ptr, on_dev = _ptr(t), 0
+            keep = t
+        if out is None:
+            out = torch.empty(count, dtype=torch.float64, device="cuda")
+        L.check(self._lib.pp_evaluate_thetas(self._h, count, ptr, on_dev, _stream(stream),
+                                             ctypes.c_void_p(out.data_ptr())))
+        self._sweep_keep = keep
+        return out
+
+    def psr_gradient(self, theta, stream=None):
+        """Parameter-shift gradient of <O> from 2 x (rotation gates) shifted
+        evaluations in one sweep: each rotation gate gets its own copy of its
+        parameter, shifted by +-pi/2, and the halves of the differences are
+        summed per parameter.  Uses a private circuit with one parameter per
+        rotation gate (built on first use)."""
+        import math
+        theta = np.asarray(theta.detach().cpu().numpy() if isinstance(theta, torch.Tensor) else theta,
+                           dtype=np.float64)
+        if getattr(self, "_psr", None) is None:
+            rot = np.nonzero(self._op >= 3)[0]
+            pexp = np.full(self.m, -1, np.int32)
+            pexp[rot] = np.arange(rot.size, dtype=np.int32)
+            c = Circuit(self.n, self._op, self._q0, self._q1, np.where(pexp >= 0, pexp, 0), max(rot.size, 1),
+                        self._obs[0], self._obs[1], self._obs[2], dtype=self.dtype, engine="dense")
+            self._psr = (c, rot)
+        c, rot = self._psr
+        base = theta[self._param[rot]] if rot.size else np.zeros(1)
+        R = rot.size
+        thetas = np.repeat(base[None, :], 2 * max(R, 1), axis=0)
+        for j in range(R):
+            thetas[2 * j, j] += math.pi / 2
+            thetas[2 * j + 1, j] -= math.pi / 2
+        vals = c.evaluate_thetas(thetas, stream=stream).cpu().numpy()
+        gexp = 0.5 * (vals[0::2] - vals[1::2])[:R]
+        grad = np.zeros(self.n_params)
+        np.add.at(grad, self._param[rot], gexp)
+        return torch.tensor(grad, dtype=torch.float64)
 
     def gradient(self, checkpoint_every=0, stream=None):
         ev = torch.empty((), dtype=torch.float64, device="cuda")
@@ -125,6 +180,9 @@ class Circuit:
         return s.as_dict()
 
     def close(self):
+        if getattr(self, "_psr", None) is not None:
+            self._psr[0].close()
+            self._psr = None
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.pp_circuit_destroy(self._h)
             self._h = ctypes.c_void_p()

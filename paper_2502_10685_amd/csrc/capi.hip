@@ -229,6 +229,21 @@ struct pp_circuit {
         int ncomp = 0;
     } gr;
 
+    // parameter sweep (pp_evaluate_thetas): per-set parameters, maps and
+    // weights back to back, and the launch descriptors of the last sweep
+    struct Sweep {
+        int64_t cap = 0;  // parameter sets the buffers hold
+        double *thetas = nullptr, *maps = nullptr;
+        void *coef = nullptr;
+        void *dbuf = nullptr;
+        size_t dcap = 0;
+        uint64_t gen = ~0ull;
+        int64_t count = -1;
+        double *out = nullptr;
+        size_t comp_off = 0, res_off = 0, pass_off = 0;
+        Staging staging;
+    } sw;
+
     Staging staging;
     pp_stats st{};
     bool evaluated = false;
@@ -247,9 +262,23 @@ void free_graph(pp_circuit *c) {
 
 void free_grad(pp_circuit *c);
 
+void free_sweep(pp_circuit *c) {
+    c->sw.staging.release();
+    dfree(c->sw.thetas);
+    dfree(c->sw.maps);
+    dfree(c->sw.coef);
+    dfree(c->sw.dbuf);
+    c->sw.cap = 0;
+    c->sw.dcap = 0;
+    c->sw.gen = ~0ull;
+    c->sw.count = -1;
+    c->sw.out = nullptr;
+}
+
 void free_plan_buffers(pp_circuit *c) {
     free_graph(c);
     free_grad(c);
+    free_sweep(c);
     dfree(c->d_ops);
     dfree(c->d_maps);
     dfree(c->d_roff);
@@ -1219,6 +1248,138 @@ pp_status ensure_grad(pp_circuit *c, int64_t every) {
 }
 
 }  // namespace
+
+// ================================================================ sweeps
+// <O> at `count` parameter vectors of one DENSE circuit in shared launches:
+// every set has its own maps and weights, all sets share the schedule, so a
+// pass of all of them is one launch (and LDS-resident circuits one launch).
+extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const double *thetas, int32_t on_device,
+                                        void *stream, double *d_expvals) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    if (count < 0 || (count > 0 && (!thetas || !d_expvals))) return fail(PP_ERR_INVALID, "bad sweep arguments");
+    if (count == 0) return PP_OK;
+    if (count > (1 << 20)) return fail(PP_ERR_INVALID, "at most 2^20 parameter sets per sweep");
+    if (!c->have_gates) return fail(PP_ERR_STATE, "gates not loaded");
+    if (!c->have_obs) return fail(PP_ERR_STATE, "observable not set");
+    if (c->engine != PP_ENGINE_DENSE || c->track)
+        return fail(PP_ERR_STATE, "parameter sweeps run on the DENSE engine without term tracking");
+    hipStream_t s = (hipStream_t)stream;
+    pp_status r = ensure_plan(c);
+    if (r != PP_OK) return r;
+    fill_plan_stats(c);
+    const pp::DensePlan &P = c->dplan;
+    auto &W = c->sw;
+    const int64_t np = std::max<int64_t>(c->g.n_params, 1);
+    const int64_t nm = std::max(P.nmaps(), 1);
+    const int64_t slots = dense_slots(c->n);
+    if (count > W.cap || W.gen != c->plan_gen) {
+        HIPCHK(hipStreamSynchronize(s));
+        if (W.gen != c->plan_gen || count > W.cap) free_sweep(c);
+        const int64_t cap = count;
+        hipError_t e = hipMalloc((void **)&W.thetas, sizeof(double) * np * cap);
+        if (e == hipSuccess) e = hipMalloc((void **)&W.maps, sizeof(double) * 9 * nm * cap);
+        if (e == hipSuccess && !P.resident) e = hipMalloc(&W.coef, (size_t)slots * c->dbytes * cap);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            free_sweep(c);
+            return fail(PP_ERR_NOMEM, "sweep buffers for " + std::to_string(count) + " parameter sets");
+        }
+        W.cap = cap;
+        W.gen = c->plan_gen;
+        W.count = -1;
+    }
+    if (c->g.n_params > 0)
+        HIPCHK(hipMemcpyAsync(W.thetas, thetas, sizeof(double) * c->g.n_params * count,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (W.count != count || W.out != d_expvals) {
+        // descriptors: compose jobs, then resident jobs or every pass's jobs
+        std::vector<unsigned char> blob;
+        auto append = [&](const void *p, size_t bytes) {
+            const size_t off = blob.size();
+            blob.resize(off + ((bytes + 255) & ~size_t(255)));
+            std::memcpy(blob.data() + off, p, bytes);
+            return off;
+        };
+        std::vector<pp::ComposeDesc> comp(count);
+        for (int64_t i = 0; i < count; ++i) {
+            comp[i] = c->h_comp;
+            comp[i].theta = W.thetas + i * np;
+            comp[i].maps = W.maps + i * nm * 9;
+        }
+        W.comp_off = append(comp.data(), comp.size() * sizeof(comp[0]));
+        if (P.resident) {
+            std::vector<pp::ResidentDesc> rd(count);
+            for (int64_t i = 0; i < count; ++i) {
+                rd[i] = c->h_res;
+                rd[i].maps = W.maps + i * nm * 9;
+                rd[i].expval_out = d_expvals + i;
+                rd[i].coef_out = nullptr;
+                rd[i].pres_out = nullptr;
+                rd[i].counters = nullptr;
+            }
+            W.res_off = append(rd.data(), rd.size() * sizeof(rd[0]));
+        } else {
+            std::vector<pp::TilePassDesc> td;
+            td.reserve((size_t)count * P.passes.size());
+            for (size_t l = 0; l < P.passes.size(); ++l)
+                for (int64_t i = 0; i < count; ++i) {
+                    pp::TilePassDesc d = c->h_pass[l];
+                    d.coef = (unsigned char *)W.coef + (size_t)i * slots * c->dbytes;
+                    d.maps = W.maps + i * nm * 9;
+                    d.tile_begin = (int32_t)(i * d.ntiles);
+                    td.push_back(d);
+                }
+            W.pass_off = td.empty() ? 0 : append(td.data(), td.size() * sizeof(td[0]));
+        }
+        if (blob.size() > W.dcap) {
+            HIPCHK(hipStreamSynchronize(s));
+            dfree(W.dbuf);
+            HIPCHK(hipMalloc(&W.dbuf, blob.size()));
+            W.dcap = blob.size();
+        }
+        r = W.staging.upload(W.dbuf, blob.data(), blob.size(), s);
+        if (r != PP_OK) return r;
+        W.count = count;
+        W.out = d_expvals;
+    }
+    unsigned char *base = (unsigned char *)W.dbuf;
+    if (P.nmaps() > 0) {
+        ProfScope ps(PC_COMPOSE, s);
+        HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + W.comp_off), (int)count, s));
+    }
+    if (P.resident) {
+        ProfScope ps(PC_RES, s);
+        HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + W.res_off), (int)count, c->n, c->dbytes, false,
+                                   s));
+        return PP_OK;
+    }
+    {
+        ProfScope ps(PC_INIT, s);
+        HIPCHK(pp::launch_dense_init(W.coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(),
+                                     s, (int)count));
+    }
+    const int shift = 2 * (c->n - P.k);
+    const int64_t ntiles = (int64_t)1 << shift;
+    if (count * ntiles > INT32_MAX) return fail(PP_ERR_INVALID, "too many tiles in one sweep launch");
+    for (size_t l = 0; l < P.passes.size(); ++l) {
+        // one launch: the sets' descriptors of pass l are consecutive
+        pp::TileGroups grp{};
+        grp.ngroups = 1;
+        grp.first_block[0] = 0;
+        grp.first_block[1] = (int32_t)(count * ntiles);
+        grp.first_desc[0] = 0;
+        grp.shift[0] = shift;
+        ProfScope ps(PC_TILE, s);
+        HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + W.pass_off) + l * count, grp, P.k, c->dbytes,
+                                    false, s));
+    }
+    {
+        ProfScope ps(PC_READOUT, s);
+        HIPCHK(pp::launch_dense_readout(W.coef, c->n, c->dbytes, d_expvals, s, (int)count));
+    }
+    c->last_stream = s;
+    return PP_OK;
+}
 
 extern "C" pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_every_gates, double *d_expval,
                                  double *d_grad) {

@@ -1244,11 +1244,13 @@ __global__ void dense_fill_kernel(T *coef, uint8_t *pres, long long size) {
     }
 }
 
-// Sequential so that repeated strings are summed in input order.
+// Sequential so that repeated strings are summed in input order; block b
+// fills the weights at coef + b * stride (one block per parameter set).
 template <typename T>
 __global__ void dense_scatter_kernel(T *coef, uint8_t *pres, int n, const uint64_t *x, const uint64_t *z,
-                                     const double *c, int nterms) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+                                     const double *c, int nterms, long long stride) {
+    if (threadIdx.x != 0) return;
+    coef += blockIdx.x * stride;
     for (int t = 0; t < nterms; ++t) {
         const long long s = morton_slot(x[t], z[t], n);
         coef[s] = (T)((double)coef[s] + c[t]);
@@ -1256,13 +1258,16 @@ __global__ void dense_scatter_kernel(T *coef, uint8_t *pres, int n, const uint64
     }
 }
 
+// Block b reads out the weights at coef + b * stride into out[b]; the same
+// fixed-order reduction for one evaluation or many.
 template <typename T>
-__global__ __launch_bounds__(256) void dense_readout_kernel(const T *coef, int n, double *out) {
+__global__ __launch_bounds__(256) void dense_readout_kernel(const T *coef, int n, double *out, long long stride) {
     __shared__ double redd[4];
+    coef += blockIdx.x * stride;
     double part = 0.0;
     for (long long j = threadIdx.x; j < (1ll << n); j += 256) part += (double)coef[zonly_slot(j, n)];
     const double tot = block_sum_d<256>(part, redd);
-    if (threadIdx.x == 0) *out = tot;
+    if (threadIdx.x == 0) out[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void dense_count_kernel(const uint8_t *pres, long long size,
@@ -1581,26 +1586,30 @@ hipError_t launch_copy_f64(const double *src, double *dst, long long count, hipS
 }
 
 hipError_t launch_dense_init(void *coef, uint8_t *pres, int n, int dtype_bytes, const uint64_t *x,
-                             const uint64_t *z, const double *c, int nterms, hipStream_t s) {
+                             const uint64_t *z, const double *c, int nterms, hipStream_t s, int count) {
     const long long size = 1ll << (2 * n);
-    const int grid = (int)((size + 255) / 256 < 4096 ? (size + 255) / 256 : 4096);
+    const long long total = size * count;
+    const int grid = (int)((total + 255) / 256 < 8192 ? (total + 255) / 256 : 8192);
     if (dtype_bytes == 8) {
-        hipLaunchKernelGGL(dense_fill_kernel<double>, dim3(grid), dim3(256), 0, s, (double *)coef, pres, size);
-        hipLaunchKernelGGL(dense_scatter_kernel<double>, dim3(1), dim3(64), 0, s, (double *)coef, pres, n, x, z, c,
-                           nterms);
+        hipLaunchKernelGGL(dense_fill_kernel<double>, dim3(grid), dim3(256), 0, s, (double *)coef, pres, total);
+        hipLaunchKernelGGL(dense_scatter_kernel<double>, dim3(count), dim3(64), 0, s, (double *)coef, pres, n, x, z,
+                           c, nterms, size);
     } else {
-        hipLaunchKernelGGL(dense_fill_kernel<float>, dim3(grid), dim3(256), 0, s, (float *)coef, pres, size);
-        hipLaunchKernelGGL(dense_scatter_kernel<float>, dim3(1), dim3(64), 0, s, (float *)coef, pres, n, x, z, c,
-                           nterms);
+        hipLaunchKernelGGL(dense_fill_kernel<float>, dim3(grid), dim3(256), 0, s, (float *)coef, pres, total);
+        hipLaunchKernelGGL(dense_scatter_kernel<float>, dim3(count), dim3(64), 0, s, (float *)coef, pres, n, x, z, c,
+                           nterms, size);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double *out, hipStream_t s) {
+hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double *out, hipStream_t s, int count) {
+    const long long size = 1ll << (2 * n);
     if (dtype_bytes == 8)
-        hipLaunchKernelGGL(dense_readout_kernel<double>, dim3(1), dim3(256), 0, s, (const double *)coef, n, out);
+        hipLaunchKernelGGL(dense_readout_kernel<double>, dim3(count), dim3(256), 0, s, (const double *)coef, n, out,
+                           size);
     else
-        hipLaunchKernelGGL(dense_readout_kernel<float>, dim3(1), dim3(256), 0, s, (const float *)coef, n, out);
+        hipLaunchKernelGGL(dense_readout_kernel<float>, dim3(count), dim3(256), 0, s, (const float *)coef, n, out,
+                           size);
     return hipGetLastError();
 }
 

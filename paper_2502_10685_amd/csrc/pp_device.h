@@ -140,9 +140,11 @@ hipError_t launch_grad_reduce(const double *partials, int nslots, int ntiles, do
 hipError_t launch_grad_accumulate(const double *rot_grad, const int32_t *slot_param, int nslots, double *grad,
                                   int nparams, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, long long count, hipStream_t s);
+// count > 1: count weight arrays of 4^n slots back to back (parameter sets)
 hipError_t launch_dense_init(void *coef, uint8_t *pres, int n, int dtype_bytes, const uint64_t *x,
-                             const uint64_t *z, const double *c, int nterms, hipStream_t s);
-hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double *out, hipStream_t s);
+                             const uint64_t *z, const double *c, int nterms, hipStream_t s, int count = 1);
+hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double *out, hipStream_t s,
+                                int count = 1);
 hipError_t launch_dense_count(const uint8_t *pres, int n, unsigned long long *out, hipStream_t s);
 hipError_t launch_dense_compact(const void *coef, const uint8_t *pres, int n, int dtype_bytes, uint64_t *x,
                                 uint64_t *z, double *c, unsigned long long *count, int *tile_flags,
