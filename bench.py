@@ -196,6 +196,15 @@ def gradient_leg(api, torch):
         c.gradient(5 * 32)
     torch.cuda.synchronize()
     t_adj = (time.perf_counter() - t0) / reps
+    cg = api.Circuit.from_workload(wc, use_graph=True)
+    cg.gradient(5 * 32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cg.gradient(5 * 32)
+    torch.cuda.synchronize()
+    t_adj_graph = (time.perf_counter() - t0) / reps
+    cg.close()
     pc, rot = c._psr
     base = wc.theta[wc.param[rot]]
     th = np.repeat(base[None, :], 2 * rot.size, axis=0)
@@ -214,7 +223,8 @@ def gradient_leg(api, torch):
     u_eval = int(count_updates(api, [wc], "f64")[0][0])
     c.close()
     return {"workload": "n=8 HEA-40 (1280 gates, 960 theta), TFIM, FP64",
-            "adjoint_ms": t_adj * 1e3, "psr_sweep_ms": t_psr * 1e3, "psr_evaluations": int(th.shape[0]),
+            "adjoint_ms": t_adj * 1e3, "adjoint_graph_ms": t_adj_graph * 1e3,
+            "psr_sweep_ms": t_psr * 1e3, "psr_evaluations": int(th.shape[0]),
             "psr_evaluations_per_s": th.shape[0] / t_psr,
             "psr_updates_per_s": th.shape[0] * u_eval / t_psr,
             "adjoint_speedup_vs_psr": t_psr / t_adj,

@@ -84,7 +84,11 @@ typedef enum pp_option {
                                0 = autotuned default */
     PP_OPT_MAX_TERMS = 2,   /* SPARSE: capacity of the term list (default
                                min(4^n, 2^24)); the buffers hold 2x this */
-    PP_OPT_USE_GRAPH = 3,   /* 1: replay a captured hipGraph for evaluate */
+    PP_OPT_USE_GRAPH = 3,   /* 1: replay a captured hipGraph for pp_evaluate
+                               (tiled DENSE) and for pp_gradient (the whole
+                               Heisenberg + adjoint sweep, a training step's
+                               launch sequence); theta is read from device
+                               memory at replay */
     PP_OPT_BLOCK = 4        /* threads per workgroup (64..1024), 0 = default */
 } pp_option;
 

@@ -227,6 +227,11 @@ struct pp_circuit {
         double *ckpt = nullptr, *rbuf = nullptr, *partials = nullptr, *rot_grad = nullptr;
         int32_t *slot_param = nullptr;
         int ncomp = 0;
+        // graph of one gradient (PP_OPT_USE_GRAPH): results land in out
+        // (<O>, then the gradient) and are copied to the caller's arrays
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        double *out = nullptr;
     } gr;
 
     // parameter sweep (pp_evaluate_thetas): per-set parameters, maps and
@@ -291,8 +296,18 @@ void free_plan_buffers(pp_circuit *c) {
     c->plan_valid = false;
 }
 
+void free_grad_graph(pp_circuit *c) {
+    auto &G = c->gr;
+    if (G.gexec) (void)hipGraphExecDestroy(G.gexec);
+    if (G.graph) (void)hipGraphDestroy(G.graph);
+    G.gexec = nullptr;
+    G.graph = nullptr;
+    dfree(G.out);
+}
+
 void free_grad(pp_circuit *c) {
     auto &G = c->gr;
+    free_grad_graph(c);
     if (!G.hops && !G.ckpt && !G.valid) return;
     dfree(G.hops); dfree(G.fops); dfree(G.hmaps); dfree(G.fmaps);
     dfree(G.hroff); dfree(G.hrparam); dfree(G.froff); dfree(G.frparam);
@@ -303,6 +318,7 @@ void free_grad(pp_circuit *c) {
 
 void free_state_buffers(pp_circuit *c) {
     free_graph(c);
+    free_grad_graph(c);  // captured with this circuit's weight buffer
     dfree(c->coef);
     dfree(c->pres);
     dfree(c->d_counters);
@@ -1381,6 +1397,8 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
     return PP_OK;
 }
 
+pp_status enqueue_gradient_body(pp_circuit *c, hipStream_t s, double *d_expval, double *d_grad);
+
 extern "C" pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_every_gates, double *d_expval,
                                  double *d_grad) {
     pp_status r = check_ready(c);
@@ -1393,6 +1411,50 @@ extern "C" pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint
     const int64_t every = checkpoint_every_gates > 0 ? checkpoint_every_gates : 256;
     if ((r = ensure_grad(c, every)) != PP_OK) return r;
     hipStream_t s = (hipStream_t)stream;
+    auto &G = c->gr;
+    if (c->use_graph) {
+        const int np = c->g.n_params;
+        if (!G.gexec) {
+            HIPCHK(dalloc(&G.out, (size_t)1 + np));
+            hipStream_t cs;
+            HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                g_prof.capturing++;
+                r = enqueue_gradient_body(c, cs, G.out, G.out + 1);
+                g_prof.capturing--;
+                hipGraph_t gr = nullptr;
+                hipError_t e2 = hipStreamEndCapture(cs, &gr);
+                if (r == PP_OK && e2 == hipSuccess) {
+                    G.graph = gr;
+                    e2 = hipGraphInstantiate(&G.gexec, gr, nullptr, nullptr, 0);
+                }
+                if (e2 != hipSuccess && r == PP_OK) r = fail(PP_ERR_DEVICE, "gradient graph capture failed");
+            } else {
+                r = fail(PP_ERR_DEVICE, "hipStreamBeginCapture failed");
+            }
+            (void)hipStreamDestroy(cs);
+            if (r != PP_OK) {
+                free_grad_graph(c);
+                return r;
+            }
+        }
+        HIPCHK(hipGraphLaunch(G.gexec, s));
+        HIPCHK(pp::launch_copy_f64(G.out, d_expval, 1, s));
+        if (np > 0) HIPCHK(pp::launch_copy_f64(G.out + 1, d_grad, np, s));
+    } else {
+        if ((r = enqueue_gradient_body(c, s, d_expval, d_grad)) != PP_OK) return r;
+    }
+    fill_plan_stats(c);
+    c->evaluated = false;  // the dense weights now hold the forward-swept set
+    c->last_stream = s;
+    return PP_OK;
+}
+
+// The launch sequence of one gradient (no host synchronization and no
+// memsets, so it can be captured in a graph; theta is read from device
+// memory by the compose launch).
+pp_status enqueue_gradient_body(pp_circuit *c, hipStream_t s, double *d_expval, double *d_grad) {
     auto &G = c->gr;
     const pp::GradPlan &P = G.plan;
     const int n = c->n;
@@ -1447,9 +1509,6 @@ extern "C" pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint
     if (c->g.n_params > 0)
         HIPCHK(pp::launch_grad_accumulate(G.rot_grad, G.slot_param, (int)P.slot_param.size(), d_grad, c->g.n_params,
                                           s));
-    fill_plan_stats(c);
-    c->evaluated = false;  // the dense weights now hold the forward-swept set
-    c->last_stream = s;
     return PP_OK;
 }
 

@@ -107,3 +107,28 @@ def test_gradient_rejects_other_engines(api):
     c = api.Circuit.from_workload(wc, dtype="f32")
     with pytest.raises(PauliPropError):
         c.gradient()
+
+
+def test_gradient_graph_replays_match_eager(api):
+    """PP_OPT_USE_GRAPH captures the whole gradient launch sequence once;
+    replays with new theta (set between replays, with eager work and
+    synchronizations in between) give the eager results bit for bit."""
+    import torch
+    rng = np.random.default_rng(520)
+    wc = W.random_circuit(rng, 9, 300, W.obs_tfim(9))
+    eager = api.Circuit.from_workload(wc)
+    graph = api.Circuit.from_workload(wc, use_graph=True)
+    for rep in range(4):
+        th = rng.uniform(0, 2 * math.pi, size=wc.n_params)
+        eager.set_theta(th)
+        ev_e, g_e = eager.gradient(64)
+        if rep % 2:
+            graph.set_theta(torch.tensor(th, device="cuda"))
+        else:
+            graph.set_theta(th)
+        ev_g, g_g = graph.gradient(64)
+        torch.cuda.synchronize()
+        assert float(ev_g.item()) == float(ev_e.item())
+        assert np.array_equal(g_g.cpu().numpy(), g_e.cpu().numpy())
+        _ = eager.evaluate()  # unrelated eager work between replays
+        torch.cuda.synchronize()
