@@ -212,6 +212,41 @@ def hea_circuit(seed, n, layers, obs=None, name="hea"):
     return make_circuit(n, gates, p, obs, theta, name)
 
 
+def chain_zxz_gates(n: int, layers: int, repeats: int):
+    """The shape of the paper's timing ansatz (Sec. V): per layer a CX chain
+    closed into a ring 0->1, ..., (n-1)->0 (the topology drawing is not
+    available; a ring of n CX gives the stated 60.2K gates at n = 4, 50
+    layers, 100 repeats), then `repeats` blocks of RZ, RX, RZ on every qubit,
+    each rotation with its own parameter."""
+    ops, q0s, q1s, params = [], [], [], []
+    p = 0
+    for _ in range(layers):
+        if n >= 2:
+            for q in range(n):
+                ops.append(CX)
+                q0s.append(q)
+                q1s.append((q + 1) % n)
+                params.append(-1)
+        for _ in range(repeats):
+            for q in range(n):
+                for g in (RZ, RX, RZ):
+                    ops.append(g)
+                    q0s.append(q)
+                    q1s.append(-1)
+                    params.append(p)
+                    p += 1
+    return (np.array(ops, np.uint8), np.array(q0s, np.int32), np.array(q1s, np.int32),
+            np.array(params, np.int32)), p
+
+
+def chain_zxz_circuit(seed=6, n=4, layers=50, repeats=100):
+    """n = 4, 50 layers x (4 CX + 100 x 12 rotations) = 60,200 gates, O = Z_0."""
+    rng = np.random.default_rng(seed)
+    gates, p = chain_zxz_gates(n, layers, repeats)
+    theta = rng.uniform(0.0, TWO_PI, size=p)
+    return make_circuit(n, gates, p, obs_z(n, [0]), theta, name=f"chainzxz{n}x{layers}x{repeats}")
+
+
 # ---------------------------------------------------------- the five workloads
 def config1(seed=1):
     """n=4, HEA-10 (160 gates), O = Z_0, FP64."""

@@ -425,3 +425,11 @@ def test_untracked_dense_terms_are_the_nonzero_weights(api):
     small.evaluate()
     with pytest.raises(PauliPropError):
         small.terms()
+
+
+def test_chain_zxz_paper_shape(api):
+    """The 60,200-gate n = 4 circuit of the paper's timing ansatz shape."""
+    wc = W.chain_zxz_circuit()
+    c = api.Circuit.from_workload(wc)
+    print("chain zxz n=4 60200 gates", flush=True)
+    assert abs(float(c.evaluate().item()) - oracle.expval_sv(wc)) <= TOL64
