@@ -522,7 +522,7 @@ pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
     if (c->track) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, c->d_counters, 4);
     if (P.nmaps() > 0) {
         ProfScope ps(PC_COMPOSE, s);
-        HIPCHK(pp::launch_compose(c->d_comp, 1, s));
+        HIPCHK(pp::launch_compose(c->d_comp, 1, s, P.nmaps()));
     }
     if (P.resident) {
         {
@@ -1025,6 +1025,7 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
             return (int)off;
         };
         std::vector<pp::ComposeDesc> comp;
+        int comp_max = 1;
         std::vector<std::vector<int>> res_by_n(kResidentMaxN + 1);
         for (int64_t i = 0; i < count; ++i) {
             pp_circuit *c = cs[i];
@@ -1033,11 +1034,12 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
                 continue;
             }
             if (c->dplan.nmaps() > 0) comp.push_back(c->h_comp);
+            comp_max = std::max(comp_max, c->dplan.nmaps());
             if (c->dplan.resident) res_by_n[c->n].push_back((int)i);
             else B.tiled.push_back((int)i);
         }
         if (!comp.empty())
-            B.launches.push_back({0, 0, append(comp.data(), comp.size() * sizeof(comp[0])), (int)comp.size(), 0, {}});
+            B.launches.push_back({0, 0, append(comp.data(), comp.size() * sizeof(comp[0])), (int)comp.size(), comp_max, {}});
         // resident groups, largest size class first, longest circuits first
         for (int n = kResidentMaxN; n >= 1; --n) {
             auto &v = res_by_n[n];
@@ -1128,7 +1130,7 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         hipStream_t ls = L.kind == 1 ? B.aux : s;
         ProfScope ps(L.kind == 0 ? PC_COMPOSE : L.kind == 1 ? PC_RES : PC_TILE, ls);
         if (L.kind == 0) {
-            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, ls));
+            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, ls, L.nblocks));
         } else if (L.kind == 1) {
             HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, ls));
         } else {
@@ -1361,7 +1363,7 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
     unsigned char *base = (unsigned char *)W.dbuf;
     if (P.nmaps() > 0) {
         ProfScope ps(PC_COMPOSE, s);
-        HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + W.comp_off), (int)count, s));
+        HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + W.comp_off), (int)count, s, P.nmaps()));
     }
     if (P.resident) {
         ProfScope ps(PC_RES, s);
@@ -1463,7 +1465,7 @@ pp_status enqueue_gradient_body(pp_circuit *c, hipStream_t s, double *d_expval, 
     double *coef = (double *)c->coef;
     if (G.ncomp > 0) {
         ProfScope ps(PC_COMPOSE, s);
-        HIPCHK(pp::launch_compose(G.comp, G.ncomp, s));
+        HIPCHK(pp::launch_compose(G.comp, G.ncomp, s, std::max(P.heis.nmaps(), P.fwd.nmaps())));
     }
     // Heisenberg sweep, last segment first; checkpoint c(O_b) at every
     // segment start b
@@ -1667,7 +1669,7 @@ pp_status start_request(pp_server *S, ServedReq *r) {
         if (st != PP_OK) return st;
         return finish_async(S, r, S->side);
     }
-    if (c->dplan.nmaps() > 0) HIPCHK(pp::launch_compose(c->d_comp, 1, S->main));
+    if (c->dplan.nmaps() > 0) HIPCHK(pp::launch_compose(c->d_comp, 1, S->main, c->dplan.nmaps()));
     HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(),
                                  S->main));
     r->pass = 0;
@@ -1693,8 +1695,12 @@ pp_status launch_resident_batch(pp_server *S, bool *launched) {
         return a->c->dbytes != b->c->dbytes ? a->c->dbytes > b->c->dbytes : a->c->n > b->c->n;
     });
     std::vector<pp::ComposeDesc> comp;
+    int comp_max = 1;
     for (ServedReq *r : P)
-        if (r->c->dplan.nmaps() > 0) comp.push_back(r->c->h_comp);
+        if (r->c->dplan.nmaps() > 0) {
+            comp.push_back(r->c->h_comp);
+            comp_max = std::max(comp_max, r->c->dplan.nmaps());
+        }
     std::vector<pp::ResidentDesc> rd;
     for (ServedReq *r : P) {
         pp::ResidentDesc d = r->c->h_res;
@@ -1717,7 +1723,7 @@ pp_status launch_resident_batch(pp_server *S, bool *launched) {
     if (!comp.empty()) std::memcpy(Ln->h, comp.data(), cbytes);
     std::memcpy((unsigned char *)Ln->h + roff, rd.data(), rd.size() * sizeof(pp::ResidentDesc));
     HIPCHK(hipMemcpyAsync(Ln->d, Ln->h, bytes, hipMemcpyHostToDevice, Ln->st));
-    if (!comp.empty()) HIPCHK(pp::launch_compose((const pp::ComposeDesc *)Ln->d, (int)comp.size(), Ln->st));
+    if (!comp.empty()) HIPCHK(pp::launch_compose((const pp::ComposeDesc *)Ln->d, (int)comp.size(), Ln->st, comp_max));
     const pp::ResidentDesc *dres = (const pp::ResidentDesc *)((unsigned char *)Ln->d + roff);
     size_t i = 0;
     while (i < P.size()) {

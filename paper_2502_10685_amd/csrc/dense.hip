@@ -1216,21 +1216,56 @@ __device__ void gate_matrix(int op, double th, double G[9]) {
     }
 }
 
-__global__ void compose_kernel(const ComposeDesc *__restrict__ descs) {
+// One wave per map: the lanes build the matrices of 64 consecutive gates of
+// the recipe at once (their parameter loads and sincos in parallel), an
+// ordered tree of 3x3 products over the lanes multiplies them (later gates
+// on the left), and the chunk products are applied in recipe order.  Block
+// (d, y) serves descriptor d; the y blocks and the waves share its maps.
+__device__ __forceinline__ void mat3_mul(const double A[9], const double B[9], double C[9]) {
+    // C = A * B
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) C[3 * a + b] = A[3 * a] * B[b] + A[3 * a + 1] * B[3 + b] + A[3 * a + 2] * B[6 + b];
+}
+
+__global__ __launch_bounds__(256) void compose_kernel(const ComposeDesc *__restrict__ descs) {
     const ComposeDesc &d = descs[blockIdx.x];
-    for (int i = threadIdx.x; i < d.nmaps; i += blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int stride = gridDim.y * wpb;
+    for (int i = blockIdx.y * wpb + (threadIdx.x >> 6); i < d.nmaps; i += stride) {
+        const int r0 = d.roff[i], r1 = d.roff[i + 1];
         double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-        for (int r = d.roff[i]; r < d.roff[i + 1]; ++r) {
-            const int op = d.rop[r];
-            const double th = op >= 3 ? d.theta[d.rparam[r]] : 0.0;
-            double G[9], P[9];
-            gate_matrix(op, th, G);
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b)
-                    P[3 * a + b] = G[3 * a] * M[b] + G[3 * a + 1] * M[3 + b] + G[3 * a + 2] * M[6 + b];
-            for (int t = 0; t < 9; ++t) M[t] = P[t];
+        for (int c0 = r0; c0 < r1; c0 += 64) {
+            double G[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+            const int r = c0 + lane;
+            if (r < r1) {
+                const int op = d.rop[r];
+                gate_matrix(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, G);
+            }
+            // lane l holds the product of gates [c0 + l, c0 + l + w) after
+            // the step of width w; combine with the next block on the left
+#pragma unroll
+            for (int w = 1; w < 64; w <<= 1) {
+                double B[9], C[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) B[t] = __shfl_down(G[t], w, 64);
+                mat3_mul(B, G, C);
+                if ((lane & (2 * w - 1)) == 0) {
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) G[t] = C[t];
+                }
+            }
+            double P[9], C[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) P[t] = __shfl(G[t], 0, 64);
+            mat3_mul(P, M, C);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) M[t] = C[t];
         }
-        for (int t = 0; t < 9; ++t) d.maps[9ull * i + t] = M[t];
+        if (lane == 0) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) d.maps[9ull * i + t] = M[t];
+        }
     }
 }
 
@@ -1365,9 +1400,14 @@ size_t resident_lds_bytes(int n, int dtype_bytes, bool track) {
     return size * (size_t)dtype_bytes + (track ? size : 0);
 }
 
-hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s) {
+hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s, int max_maps) {
     if (ndescs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(compose_kernel, dim3(ndescs), dim3(256), 0, s, d_descs);
+    // 4 maps per block (one per wave); enough blocks per descriptor for its
+    // maps, at most 1024 across the launch's y dimension
+    int ychunks = (max_maps + 3) / 4;
+    ychunks = ychunks < 1 ? 1 : (ychunks > 1024 ? 1024 : ychunks);
+    if ((long long)ychunks * ndescs > 65536) ychunks = (int)std::max<long long>(1, 65536 / ndescs);
+    hipLaunchKernelGGL(compose_kernel, dim3(ndescs, ychunks), dim3(256), 0, s, d_descs);
     return hipGetLastError();
 }
 

@@ -123,7 +123,9 @@ struct SparsePassDesc {
 
 // ------------------------------------------------------------ launchers
 // Dense engine (dense.hip)
-hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s);
+// max_maps: the largest nmaps of the descriptors (sizes the grid; any value
+// gives the same maps)
+hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s, int max_maps = 1);
 hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int dtype_bytes, bool track,
                            hipStream_t s);
 hipError_t launch_tile_pass(const TilePassDesc *d_descs, const TileGroups &groups, int k, int dtype_bytes,
