@@ -983,6 +983,7 @@ struct BatchCache {
     hipEvent_t fork = nullptr, join = nullptr;
     struct Launch { int kind; int group_n; int off; int nd; int nblocks; pp::TileGroups tg; };
     std::vector<Launch> launches;  // kind 0 compose, 1 resident, 2 tile pass
+    int io_off = -1, io_max_n = 0;  // start/readout descriptors of the tiled circuits
     std::vector<int> tiled;        // indices of tiled circuits
     std::vector<int> single;       // indices evaluated one by one
 };
@@ -1040,6 +1041,18 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         }
         if (!comp.empty())
             B.launches.push_back({0, 0, append(comp.data(), comp.size() * sizeof(comp[0])), (int)comp.size(), comp_max, {}});
+        B.io_off = -1;
+        B.io_max_n = 0;
+        if (!B.tiled.empty()) {
+            std::vector<pp::DenseIODesc> io;
+            for (int i : B.tiled) {
+                pp_circuit *c = cs[i];
+                io.push_back(pp::DenseIODesc{c->coef, c->d_ox, c->d_oz, c->d_oc, d_expvals + i, c->n,
+                                             (int32_t)c->ox.size()});
+                B.io_max_n = std::max(B.io_max_n, c->n);
+            }
+            B.io_off = append(io.data(), io.size() * sizeof(io[0]));
+        }
         // resident groups, largest size class first, longest circuits first
         for (int n = kResidentMaxN; n >= 1; --n) {
             auto &v = res_by_n[n];
@@ -1107,11 +1120,11 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         }
     }
     unsigned char *base = (unsigned char *)B.dbuf;
-    // tiled circuits start from their observables
-    for (int i : B.tiled) {
-        pp_circuit *c = cs[i];
+    // tiled circuits start from their observables (one launch for all)
+    if (B.io_off >= 0) {
         ProfScope ps(PC_INIT, s);
-        HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+        HIPCHK(pp::launch_dense_init_many((const pp::DenseIODesc *)(base + B.io_off), (int)B.tiled.size(),
+                                          B.io_max_n, dbytes, s));
     }
     bool any_res = false;
     for (const auto &L : B.launches) any_res = any_res || L.kind == 1;
@@ -1141,10 +1154,10 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         HIPCHK(hipEventRecord(B.join, B.aux));
         HIPCHK(hipStreamWaitEvent(s, B.join, 0));
     }
-    for (int i : B.tiled) {
-        pp_circuit *c = cs[i];
+    if (B.io_off >= 0) {
         ProfScope ps(PC_READOUT, s);
-        HIPCHK(pp::launch_dense_readout(c->coef, c->n, c->dbytes, d_expvals + i, s));
+        HIPCHK(pp::launch_dense_readout_many((const pp::DenseIODesc *)(base + B.io_off), (int)B.tiled.size(), dbytes,
+                                             s));
     }
     for (int i : B.single)
         if ((r = pp_evaluate(cs[i], stream, d_expvals + i)) != PP_OK) return r;

@@ -1216,11 +1216,17 @@ __device__ void gate_matrix(int op, double th, double G[9]) {
     }
 }
 
-// One wave per map: the lanes build the matrices of 64 consecutive gates of
-// the recipe at once (their parameter loads and sincos in parallel), an
-// ordered tree of 3x3 products over the lanes multiplies them (later gates
-// on the left), and the chunk products are applied in recipe order.  Block
-// (d, y) serves descriptor d; the y blocks and the waves share its maps.
+// Maps are composed by one lane when their recipe is short and by a whole
+// wave when it is long (the rule depends on the map alone, so a circuit's
+// maps are the same bits however it is batched).  A wave takes 64
+// consecutive maps: each lane folds its short recipe in order; then for each
+// long recipe of the 64, the lanes build the matrices of 64 consecutive
+// gates at once (their parameter loads and sincos in parallel), an ordered
+// tree of 3x3 products over the lanes multiplies them (later gates on the
+// left), and the chunk products are applied in recipe order.  Block (d, y)
+// serves descriptor d; its y blocks and their waves share its maps.
+constexpr int kShortRecipe = 8;
+
 __device__ __forceinline__ void mat3_mul(const double A[9], const double B[9], double C[9]) {
     // C = A * B
     for (int a = 0; a < 3; ++a)
@@ -1231,40 +1237,63 @@ __global__ __launch_bounds__(256) void compose_kernel(const ComposeDesc *__restr
     const ComposeDesc &d = descs[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
-    const int stride = gridDim.y * wpb;
-    for (int i = blockIdx.y * wpb + (threadIdx.x >> 6); i < d.nmaps; i += stride) {
-        const int r0 = d.roff[i], r1 = d.roff[i + 1];
-        double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-        for (int c0 = r0; c0 < r1; c0 += 64) {
-            double G[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-            const int r = c0 + lane;
-            if (r < r1) {
-                const int op = d.rop[r];
-                gate_matrix(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, G);
-            }
-            // lane l holds the product of gates [c0 + l, c0 + l + w) after
-            // the step of width w; combine with the next block on the left
-#pragma unroll
-            for (int w = 1; w < 64; w <<= 1) {
-                double B[9], C[9];
-#pragma unroll
-                for (int t = 0; t < 9; ++t) B[t] = __shfl_down(G[t], w, 64);
-                mat3_mul(B, G, C);
-                if ((lane & (2 * w - 1)) == 0) {
-#pragma unroll
-                    for (int t = 0; t < 9; ++t) G[t] = C[t];
+    const int wstride = gridDim.y * wpb;
+    for (int w0 = (blockIdx.y * wpb + (threadIdx.x >> 6)) * 64; w0 < d.nmaps; w0 += wstride * 64) {
+        const int i = w0 + lane;
+        bool longr = false;
+        if (i < d.nmaps) {
+            const int r0 = d.roff[i], r1 = d.roff[i + 1];
+            longr = r1 - r0 > kShortRecipe;
+            if (!longr) {
+                double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+                for (int r = r0; r < r1; ++r) {
+                    const int op = d.rop[r];
+                    double G[9], P[9];
+                    gate_matrix(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, G);
+                    mat3_mul(G, M, P);
+                    for (int t = 0; t < 9; ++t) M[t] = P[t];
                 }
+                for (int t = 0; t < 9; ++t) d.maps[9ull * i + t] = M[t];
             }
-            double P[9], C[9];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) P[t] = __shfl(G[t], 0, 64);
-            mat3_mul(P, M, C);
-#pragma unroll
-            for (int t = 0; t < 9; ++t) M[t] = C[t];
         }
-        if (lane == 0) {
+        uint64_t todo = __ballot(longr);
+        while (todo) {
+            const int l = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int m = w0 + l;
+            const int r0 = d.roff[m], r1 = d.roff[m + 1];
+            double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+            for (int c0 = r0; c0 < r1; c0 += 64) {
+                double G[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+                const int r = c0 + lane;
+                if (r < r1) {
+                    const int op = d.rop[r];
+                    gate_matrix(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, G);
+                }
+                // lane l holds the product of gates [c0 + l, c0 + l + w) after
+                // the step of width w; combine with the next block on the left
 #pragma unroll
-            for (int t = 0; t < 9; ++t) d.maps[9ull * i + t] = M[t];
+                for (int w = 1; w < 64; w <<= 1) {
+                    double B[9], C[9];
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) B[t] = __shfl_down(G[t], w, 64);
+                    mat3_mul(B, G, C);
+                    if ((lane & (2 * w - 1)) == 0) {
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) G[t] = C[t];
+                    }
+                }
+                double P[9], C[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) P[t] = __shfl(G[t], 0, 64);
+                mat3_mul(P, M, C);
+#pragma unroll
+                for (int t = 0; t < 9; ++t) M[t] = C[t];
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int t = 0; t < 9; ++t) d.maps[9ull * m + t] = M[t];
+            }
         }
     }
 }
@@ -1303,6 +1332,38 @@ __global__ __launch_bounds__(256) void dense_readout_kernel(const T *coef, int n
     for (long long j = threadIdx.x; j < (1ll << n); j += 256) part += (double)coef[zonly_slot(j, n)];
     const double tot = block_sum_d<256>(part, redd);
     if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ void many_fill_kernel(const DenseIODesc *__restrict__ descs) {
+    const DenseIODesc &d = descs[blockIdx.y];
+    T *coef = reinterpret_cast<T *>(d.coef);
+    const long long size = 1ll << (2 * d.n);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < size;
+         i += (long long)gridDim.x * blockDim.x)
+        coef[i] = (T)0;
+}
+
+template <typename T>
+__global__ void many_scatter_kernel(const DenseIODesc *__restrict__ descs) {
+    if (threadIdx.x != 0) return;
+    const DenseIODesc &d = descs[blockIdx.x];
+    T *coef = reinterpret_cast<T *>(d.coef);
+    for (int t = 0; t < d.nterms; ++t) {
+        const long long s = morton_slot(d.obs_x[t], d.obs_z[t], d.n);
+        coef[s] = (T)((double)coef[s] + d.obs_c[t]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void many_readout_kernel(const DenseIODesc *__restrict__ descs) {
+    __shared__ double redd[4];
+    const DenseIODesc &d = descs[blockIdx.x];
+    const T *coef = reinterpret_cast<const T *>(d.coef);
+    double part = 0.0;
+    for (long long j = threadIdx.x; j < (1ll << d.n); j += 256) part += (double)coef[zonly_slot(j, d.n)];
+    const double tot = block_sum_d<256>(part, redd);
+    if (threadIdx.x == 0) *d.out = tot;
 }
 
 __global__ __launch_bounds__(256) void dense_count_kernel(const uint8_t *pres, long long size,
@@ -1402,9 +1463,9 @@ size_t resident_lds_bytes(int n, int dtype_bytes, bool track) {
 
 hipError_t launch_compose(const ComposeDesc *d_descs, int ndescs, hipStream_t s, int max_maps) {
     if (ndescs <= 0) return hipSuccess;
-    // 4 maps per block (one per wave); enough blocks per descriptor for its
+    // 256 maps per block (64 per wave); enough blocks per descriptor for its
     // maps, at most 1024 across the launch's y dimension
-    int ychunks = (max_maps + 3) / 4;
+    int ychunks = (max_maps + 255) / 256;
     ychunks = ychunks < 1 ? 1 : (ychunks > 1024 ? 1024 : ychunks);
     if ((long long)ychunks * ndescs > 65536) ychunks = (int)std::max<long long>(1, 65536 / ndescs);
     hipLaunchKernelGGL(compose_kernel, dim3(ndescs, ychunks), dim3(256), 0, s, d_descs);
@@ -1650,6 +1711,29 @@ hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double
     else
         hipLaunchKernelGGL(dense_readout_kernel<float>, dim3(count), dim3(256), 0, s, (const float *)coef, n, out,
                            size);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_init_many(const DenseIODesc *d_descs, int nd, int max_n, int dtype_bytes, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    const long long size = 1ll << (2 * max_n);
+    const int gx = (int)((size + 255) / 256 < 1024 ? (size + 255) / 256 : 1024);
+    if (dtype_bytes == 8) {
+        hipLaunchKernelGGL(many_fill_kernel<double>, dim3(gx, nd), dim3(256), 0, s, d_descs);
+        hipLaunchKernelGGL(many_scatter_kernel<double>, dim3(nd), dim3(64), 0, s, d_descs);
+    } else {
+        hipLaunchKernelGGL(many_fill_kernel<float>, dim3(gx, nd), dim3(256), 0, s, d_descs);
+        hipLaunchKernelGGL(many_scatter_kernel<float>, dim3(nd), dim3(64), 0, s, d_descs);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_readout_many(const DenseIODesc *d_descs, int nd, int dtype_bytes, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(many_readout_kernel<double>, dim3(nd), dim3(256), 0, s, d_descs);
+    else
+        hipLaunchKernelGGL(many_readout_kernel<float>, dim3(nd), dim3(256), 0, s, d_descs);
     return hipGetLastError();
 }
 

@@ -98,6 +98,16 @@ struct TileGroups {
     int32_t shift[kMaxTileGroups];
 };
 
+// Start weights and readout of one tiled circuit of a batch: the observable
+// is scattered into its 4^n weights, and <O> read out into *out.
+struct DenseIODesc {
+    void *coef;
+    const uint64_t *obs_x, *obs_z;
+    const double *obs_c;
+    double *out;
+    int32_t n, nterms;
+};
+
 // Per-circuit composition job: maps[i] = product of the gate matrices of
 // recipe entries [roff[i], roff[i+1]) in Heisenberg order.
 struct ComposeDesc {
@@ -147,6 +157,10 @@ hipError_t launch_dense_init(void *coef, uint8_t *pres, int n, int dtype_bytes, 
                              const uint64_t *z, const double *c, int nterms, hipStream_t s, int count = 1);
 hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double *out, hipStream_t s,
                                 int count = 1);
+// the same for the nd circuits of a batch (one fill, one scatter launch;
+// one readout launch), each circuit with the single-circuit arithmetic
+hipError_t launch_dense_init_many(const DenseIODesc *d_descs, int nd, int max_n, int dtype_bytes, hipStream_t s);
+hipError_t launch_dense_readout_many(const DenseIODesc *d_descs, int nd, int dtype_bytes, hipStream_t s);
 hipError_t launch_dense_count(const uint8_t *pres, int n, unsigned long long *out, hipStream_t s);
 hipError_t launch_dense_compact(const void *coef, const uint8_t *pres, int n, int dtype_bytes, uint64_t *x,
                                 uint64_t *z, double *c, unsigned long long *count, int *tile_flags,
