@@ -332,13 +332,47 @@ static DensePlan plan_dense_core(const GateList &g, int k, int low, const PlanOp
                 }
             }
             if (__builtin_popcount(S) >= k) break;
-            int64_t best = -1;
+            // grow the tile by the wires of one ready gate: the one after
+            // which the most gates become schedulable (earliest on ties);
+            // without lookahead simply the earliest
+            int64_t best = -1, best_gain = -1;
             for (int q = 0; q < n; ++q) {
                 if (head[q] >= wq[q].size()) continue;
                 const int64_t h = wq[q][head[q]];
                 if (!ready(h)) continue;
                 if (__builtin_popcount(S | wires(h)) > k) continue;
-                if (best < 0 || h < best) best = h;
+                int64_t gain = 0;
+                if (o.lookahead) {
+                    const uint32_t S2 = S | wires(h);
+                    std::vector<size_t> hd(head);
+                    auto rdy = [&](int64_t x) {
+                        const uint32_t w = wires(x);
+                        for (int r = 0; r < n; ++r)
+                            if ((w >> r) & 1u)
+                                if (hd[r] >= wq[r].size() || wq[r][hd[r]] != x) return false;
+                        return true;
+                    };
+                    bool prog = true;
+                    while (prog) {
+                        prog = false;
+                        for (int r = 0; r < n; ++r) {
+                            if (!((S2 >> r) & 1u)) continue;
+                            while (hd[r] < wq[r].size()) {
+                                const int64_t x = wq[r][hd[r]];
+                                const uint32_t w = wires(x);
+                                if ((w & ~S2) || !rdy(x)) break;
+                                for (int t = 0; t < n; ++t)
+                                    if ((w >> t) & 1u) hd[t]++;
+                                ++gain;
+                                prog = true;
+                            }
+                        }
+                    }
+                }
+                if (gain > best_gain || (gain == best_gain && h < best)) {
+                    best = h;
+                    best_gain = gain;
+                }
             }
             if (best < 0) break;
             S |= wires(best);

@@ -64,6 +64,7 @@ struct PlanOptions {
     bool compose = true;
     bool group = true;  // pack ops on a common digit pair into GROUP ops
     bool reorder = true;
+    bool lookahead = true;  // grow a tile by the gate that unlocks the most gates
     bool forward = false;
     int64_t g_begin = 0, g_end = -1;
     const std::vector<int32_t> *slot = nullptr;
