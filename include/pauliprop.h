@@ -245,9 +245,10 @@ PP_API void pp_server_destroy(pp_server *s);
  * built or a kernel launched):
  *   PP_TUNE_TILE_QUBITS: index = n (8..16), value = default tile qubits k
  *                        (4..7) for circuits without PP_OPT_TILE_QUBITS;
- *   PP_TUNE_TILE_KERNEL: index = k (4..6), value = 0 one 256-thread
- *                        workgroup per tile, 1 persistent 256-thread
- *                        workgroups that prefetch the next tile, 2 one
+ *   PP_TUNE_TILE_KERNEL: index = k (4..7), value = 0 one 256-thread
+ *                        workgroup per tile (512 for k = 7), 1 persistent
+ *                        workgroups (256 threads; 512 for k = 7) that
+ *                        prefetch the next tile, 2 (k <= 6) one
  *                        single-wave (64-thread) workgroup per tile, 3
  *                        (k = 6 only) one wave per tile holding the tile
  *                        in registers, LDS used only to change which three

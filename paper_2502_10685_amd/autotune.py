@@ -109,11 +109,11 @@ def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None, res
         for c in circs:
             c.close()
     # 1. kernel variant per tile size k, on circuits with n = k + 3 tiled at k
-    for k in (4, 5, 6):
+    for k in (4, 5, 6, 7):
         n = k + 3
         circs = _probe_batch(api, n, _count_for(n), m, dtype, seed=9000 + k, tile_qubits=k)
         best, times = None, {}
-        for v in ((0, 1, 2, 3, 4) if k == 6 else (0, 1, 2)):
+        for v in {6: (0, 1, 2, 3, 4), 7: (0, 1)}.get(k, (0, 1, 2)):
             L.tune_set(L.PP_TUNE_TILE_KERNEL, k, v)
             times[v] = _time_batch(api, circs)
             if best is None or times[v] < times[best]:

@@ -2045,8 +2045,9 @@ extern "C" pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value) 
         return PP_OK;
     }
     if (key == PP_TUNE_TILE_KERNEL) {
-        if (index < 4 || index > 6 || value < 0 || value > 4 || (value >= 3 && index != 6))
-            return fail(PP_ERR_INVALID, "tile kernel: k in 4..6, value 0..4 (3, 4: k = 6 only)");
+        if (index < 4 || index > 7 || value < 0 || value > 4 || (value >= 3 && index != 6) ||
+            (index == 7 && value == 2))
+            return fail(PP_ERR_INVALID, "tile kernel: k in 4..7, value 0..4 (2: k <= 6; 3, 4: k = 6 only)");
         pp::set_tile_kernel_variant(index, value);
         return PP_OK;
     }
@@ -2065,7 +2066,7 @@ extern "C" pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value)
         *value = g_tile_qubits[index];
         return PP_OK;
     }
-    if (key == PP_TUNE_TILE_KERNEL && index >= 4 && index <= 6) {
+    if (key == PP_TUNE_TILE_KERNEL && index >= 4 && index <= 7) {
         *value = pp::tile_kernel_variant(index);
         return PP_OK;
     }

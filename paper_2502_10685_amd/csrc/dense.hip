@@ -601,7 +601,7 @@ struct TileLoc {
     unsigned voff;  // bytes
 };
 
-template <typename T, int K>
+template <typename T, int K, int BLOCK>
 __device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ descs, const TileGroups &grp, int b,
                                                int tid) {
     int g = 0;
@@ -621,18 +621,27 @@ __device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ 
         base |= (t & 3ll) << (2 * q);
         t >>= 2;
     }
-    return TileLoc{d, base, (unsigned)deposit_digits(tid, qubits, 0, 4) * (unsigned)sizeof(T)};
+    // the thread index supplies the low bits of the slot index (digits 0-3,
+    // and the low bit of digit 4 for 512 threads); deposits of disjoint bits OR
+    return TileLoc{d, base, (unsigned)deposit_digits(tid, qubits, 0, BLOCK > 256 ? 5 : 4) * (unsigned)sizeof(T)};
 }
 
-template <typename T, int K>
+template <typename T, int K, int BLOCK>
 __device__ __forceinline__ unsigned stream_soff(uint64_t qubits, int r) {
-    return (unsigned)deposit_digits(r << 8, qubits, 4, K) * (unsigned)sizeof(T);
+    return (unsigned)deposit_digits(r * BLOCK, qubits, 4, K) * (unsigned)sizeof(T);
 }
 
+// 256 threads for tiles up to 4^6 slots (3 workgroups per CU); 512 threads
+// and one workgroup per CU for 4^7 slots (its LDS tile is 128 KiB in FP64)
+template <int K>
+constexpr int kStreamBlock = K >= 7 ? 512 : 256;
+template <int K>
+constexpr int kStreamWaves = K >= 7 ? 2 : 3;
+
 template <typename T, int K>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void tile_stream_kernel(
-    const TilePassDesc *__restrict__ descs, TileGroups grp) {
-    constexpr int BLOCK = 256;
+__global__ __launch_bounds__(kStreamBlock<K>) __attribute__((amdgpu_waves_per_eu(kStreamWaves<K>)))
+void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) {
+    constexpr int BLOCK = kStreamBlock<K>;
     constexpr int size = 1 << (2 * K);
     constexpr int PER = size / BLOCK;
     static_assert(K >= 4, "the thread index supplies four digits");
@@ -645,13 +654,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void t
     const int total = grp.first_block[grp.ngroups];
     int blk = blockIdx.x;
     if (blk >= total) return;
-    TileLoc cur = locate_tile<T, K>(descs, grp, blk, tid);
+    TileLoc cur = locate_tile<T, K, BLOCK>(descs, grp, blk, tid);
     T pre[PER];
     {
         const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(cur.d->coef) + cur.base);
         const uint64_t qubits = cur.d->qubits;
 #pragma unroll
-        for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, cur.voff, stream_soff<T, K>(qubits, r));
+        for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, cur.voff, stream_soff<T, K, BLOCK>(qubits, r));
     }
     long long tcount = 0, updates = 0;
     for (;;) {
@@ -675,11 +684,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void t
         const bool has_next = nblk < total;
         TileLoc nxt = cur;
         if (has_next) {
-            nxt = locate_tile<T, K>(descs, grp, nblk, tid);
+            nxt = locate_tile<T, K, BLOCK>(descs, grp, nblk, tid);
             const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
             const uint64_t qubits = nxt.d->qubits;
 #pragma unroll
-            for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K>(qubits, r));
+            for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
         }
         if (tid < cn) {
             oc.ops[tid] = opr;
@@ -693,7 +702,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void t
             const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(cur.d->coef) + cur.base);
             const uint64_t qubits = cur.d->qubits;
 #pragma unroll
-            for (int r = 0; r < PER; ++r) BufIO<T>::st(rs, cur.voff, stream_soff<T, K>(qubits, r), lc[stid ^ sw(r * BLOCK)]);
+            for (int r = 0; r < PER; ++r) BufIO<T>::st(rs, cur.voff, stream_soff<T, K, BLOCK>(qubits, r), lc[stid ^ sw(r * BLOCK)]);
         }
         if (!has_next) break;
         blk = nblk;
@@ -1528,8 +1537,8 @@ hipError_t launch_resident(const ResidentDesc *d_descs, int ndescs, int n, int d
 }
 
 // defaults measured on MI355X: one wave per 4^5-slot tile; persistent
-// prefetching workgroups for 4^6-slot tiles
-static int g_tile_variant[8] = {0, 0, 0, 0, 0, 2, 1, 0};
+// prefetching workgroups for 4^6- and 4^7-slot tiles
+static int g_tile_variant[8] = {0, 0, 0, 0, 0, 2, 1, 1};
 void set_tile_kernel_variant(int k, int variant) {
     if (k >= 0 && k < 8) g_tile_variant[k] = variant;
 }
@@ -1582,20 +1591,21 @@ static hipError_t launch_tile_t(const TilePassDesc *d, const TileGroups &grp, si
         hipLaunchKernelGGL(fn, dim3(nblocks), dim3(64), lds, s, d, grp);
         return hipGetLastError();
     }
-    if (!TRACK && K <= 6 && g_tile_variant[K] == 1 && max_n <= 14) {
-        auto fn = tile_stream_kernel<T, (K <= 6 ? K : 6)>;
+    if (!TRACK && g_tile_variant[K] == 1 && max_n <= 14) {
+        auto fn = tile_stream_kernel<T, K>;
+        constexpr int SB = kStreamBlock<K>;
         static int rb = 0;
         if (!rb) {
             hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                max_lds_bytes() - (int)kStaticLdsReserve);
             if (e != hipSuccess) return e;
             int per_cu = 0;
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, SB, lds);
             if (e != hipSuccess) return e;
             rb = std::max(per_cu, 1) * num_cus();
         }
         const int grid = nblocks < rb ? nblocks : rb;
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, s, d, grp);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(SB), lds, s, d, grp);
         return hipGetLastError();
     }
     constexpr int TB = K >= 7 ? 512 : 256;

@@ -301,7 +301,7 @@ def test_invalid_inputs(api):
         c.evaluate()  # theta never set
 
 
-@pytest.mark.parametrize("k", [4, 5, 6])
+@pytest.mark.parametrize("k", [4, 5, 6, 7])
 def test_tile_kernel_variants_bitwise(api, k):
     """The three tile-pass kernels (one 256-thread workgroup per tile,
     persistent prefetching workgroups, one wave per tile) run the same ops in
@@ -314,14 +314,14 @@ def test_tile_kernel_variants_bitwise(api, k):
     vals = []
     old = L.tune_get(L.PP_TUNE_TILE_KERNEL, k)
     try:
-        for variant in (0, 1, 2):
+        for variant in ((0, 1, 2) if k <= 6 else (0, 1)):
             L.tune_set(L.PP_TUNE_TILE_KERNEL, k, variant)
             c = api.Circuit.from_workload(wc, engine="dense", tile_qubits=k)
             vals.append(float(c.evaluate().item()))
             c.close()
     finally:
         L.tune_set(L.PP_TUNE_TILE_KERNEL, k, old)
-    assert vals[0] == vals[1] == vals[2], vals
+    assert all(v == vals[0] for v in vals), vals
     assert abs(vals[0] - sv) <= TOL64
 
 
