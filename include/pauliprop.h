@@ -83,7 +83,8 @@ typedef enum pp_option {
     PP_OPT_TILE_QUBITS = 1, /* DENSE, n >= 8: qubits per LDS tile (4..7);
                                0 = autotuned default */
     PP_OPT_MAX_TERMS = 2,   /* SPARSE: capacity of the term list (default
-                               min(4^n, 2^24)); the buffers hold 2x this */
+                               min(4^n, 2^24), at most 2^29); the buffers
+                               hold 2x this */
     PP_OPT_USE_GRAPH = 3,   /* 1: replay a captured hipGraph for pp_evaluate
                                (tiled DENSE) and for pp_gradient (the whole
                                Heisenberg + adjoint sweep, a training step's

@@ -71,6 +71,8 @@ __global__ void compact_to_sparse_count_kernel(const unsigned long long *total, 
 
 constexpr int kResidentMaxN = 7;
 constexpr int kDenseMaxN = 16;
+// 32-bit tile offsets in the sparse kernels: 2x the capacity stays below 2^31
+constexpr int64_t kSparseMaxTerms = (int64_t)1 << 29;
 constexpr int kAutoDenseMaxN = 13;
 constexpr int kLowQubits = 2;
 
@@ -326,6 +328,7 @@ void free_state_buffers(pp_circuit *c) {
     dfree(c->d_partials);
     for (void *&p : c->sb_base) dfree(p);
     dfree(c->sb.count);
+    dfree(c->sb.scan);
     dfree(c->sb.updates);
     dfree(c->sb.hist);
     dfree(c->sb.tile_flags);
@@ -383,7 +386,8 @@ pp_status ensure_state(pp_circuit *c) {
         c->sb.x2 = (uint64_t *)c->sb_base[3];
         c->sb.z2 = (uint64_t *)c->sb_base[4];
         c->sb.c2 = c->sb_base[5];
-        HIPCHK(dalloc(&c->sb.count, 4));
+        HIPCHK(dalloc(&c->sb.count, 8));
+        HIPCHK(dalloc(&c->sb.scan, 256));
         HIPCHK(dalloc(&c->sb.updates, 1));
         HIPCHK(dalloc(&c->sb.hist, (size_t)256 * tiles));
         HIPCHK(dalloc(&c->sb.tile_flags, (size_t)tiles));
@@ -784,7 +788,7 @@ pp_status pp_circuit_set_option(pp_circuit *c, pp_option key, int64_t value) {
         free_graph(c);
         return PP_OK;
     case PP_OPT_MAX_TERMS:
-        if (value < 0) return fail(PP_ERR_INVALID, "max terms must be >= 0");
+        if (value < 0 || value > kSparseMaxTerms) return fail(PP_ERR_INVALID, "max terms must be 0..2^29");
         c->max_terms = value;
         free_state_buffers(c);
         free_plan_buffers(c);
@@ -905,7 +909,8 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
         tmp.max_tiles = tiles;
         bool ok = true;
         for (int i = 0; i < 6 && ok; ++i) ok = hipMalloc(&tmp_base[i], (size_t)slots * 8) == hipSuccess;
-        ok = ok && hipMalloc((void **)&tmp.count, 4 * sizeof(long long)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&tmp.count, 8 * sizeof(long long)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&tmp.scan, 256 * sizeof(long long)) == hipSuccess;
         ok = ok && hipMalloc((void **)&tmp.updates, sizeof(unsigned long long)) == hipSuccess;
         ok = ok && hipMalloc((void **)&tmp.hist, (size_t)256 * tiles * sizeof(unsigned)) == hipSuccess;
         ok = ok && hipMalloc((void **)&tmp.tile_flags, (size_t)std::max<int64_t>(tiles, slots / 4096 + 1) * sizeof(int)) ==
@@ -957,6 +962,7 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
     }
     for (void *&p : tmp_base) dfree(p);
     dfree(tmp.count);
+    dfree(tmp.scan);
     dfree(tmp.updates);
     dfree(tmp.hist);
     dfree(tmp.tile_flags);

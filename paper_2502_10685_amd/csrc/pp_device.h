@@ -175,7 +175,9 @@ struct SparseBuffers {
     void *c;
     uint64_t *x2, *z2;    // ping-pong for the sort
     void *c2;
-    long long *count;     // [0] live strings, [1] overflow flag
+    long long *count;     // [0] live strings, [1] overflow flag, [2] first child,
+                          // [3] count before a merge, [4] scan total (8 words)
+    long long *scan;      // per-workgroup sums of the multi-workgroup scan (256)
     unsigned long long *updates;
     unsigned int *hist;   // radix histograms
     int *tile_flags;      // decoupled look-back state

@@ -26,6 +26,7 @@ constexpr int SP_ITEMS = 8;
 constexpr int SP_TILE = SP_BLOCK * SP_ITEMS;  // 2048 terms per block
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int SP_GRID = 2048;  // cap on the workgroups of a tile kernel
 
 template <typename T>
 __device__ __forceinline__ double ldc(const void *p, long long i) { return (double)((const T *)p)[i]; }
@@ -73,51 +74,95 @@ __device__ __forceinline__ bool rot_child(int op, int q, uint64_t x, uint64_t z,
     return xb;
 }
 
-// phase 1: count anticommuting terms per block
+// Every kernel below covers only the live tiles: the grid is capped at
+// SP_GRID workgroups and each workgroup strides over tiles, the live count
+// being read from device memory, so a small term set costs a small pass.
+__device__ __forceinline__ long long live_tiles(long long T) { return (T + SP_TILE - 1) / SP_TILE; }
+
+// phase 1: count anticommuting terms per tile
 __global__ __launch_bounds__(SP_BLOCK) void pass_count_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z,
                                                              const long long *__restrict__ count,
                                                              const uint32_t *__restrict__ codes, SparsePassDesc p,
                                                              int *__restrict__ bcounts) {
     __shared__ int red[SP_BLOCK / 64];
     const long long T = count[0];
-    const long long b0 = (long long)blockIdx.x * SP_TILE;
-    int mine = 0;
-    if (p.rot_op >= 3 && b0 < T) {
-        for (int it = 0; it < SP_ITEMS; ++it) {
-            const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-            if (i < T) {
-                uint64_t xx = x[i], zz = z[i];
-                unsigned neg = 0;
-                clifford_apply(xx, zz, neg, codes, p.g_begin, p.g_end);
-                uint64_t fx, fz;
-                double sg;
-                mine += rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg) ? 1 : 0;
+    const long long L = live_tiles(T);
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        const long long b0 = t * SP_TILE;
+        int mine = 0;
+        if (p.rot_op >= 3) {
+            for (int it = 0; it < SP_ITEMS; ++it) {
+                const long long i = b0 + it * SP_BLOCK + threadIdx.x;
+                if (i < T) {
+                    uint64_t xx = x[i], zz = z[i];
+                    unsigned neg = 0;
+                    clifford_apply(xx, zz, neg, codes, p.g_begin, p.g_end);
+                    uint64_t fx, fz;
+                    double sg;
+                    mine += rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg) ? 1 : 0;
+                }
             }
         }
-    }
-    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mine;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < SP_BLOCK / 64; ++w) t += red[w];
-        bcounts[blockIdx.x] = t;
+        for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int s = 0;
+            for (int w = 0; w < SP_BLOCK / 64; ++w) s += red[w];
+            bcounts[t] = s;
+        }
+        __syncthreads();
     }
 }
 
-// phase 2: exclusive scan of the block counts; appends the children after the
-// live terms, flags overflow, and counts term updates.
-__global__ __launch_bounds__(1024) void pass_scan_kernel(int *__restrict__ bcounts, int nblocks, long long *__restrict__ count,
-                                                        long long cap2, unsigned long long *__restrict__ updates,
-                                                        int ngates, long long *__restrict__ child_base) {
+// Exclusive scan, in place, of a[0, len) with len = mult * (live tiles of
+// count[0]).  SCAN_BLOCKS workgroups each own one contiguous chunk: the first
+// kernel sums every chunk, the second adds to each chunk the sums of the
+// chunks before it and scans it; the last workgroup leaves the grand total.
+constexpr int SCAN_BLOCKS = 256;
+
+__device__ __forceinline__ void scan_chunk(long long len, long long &lo, long long &hi) {
+    const long long chunk = (len + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    lo = (long long)blockIdx.x * chunk;
+    hi = lo + chunk < len ? lo + chunk : len;
+}
+
+__device__ __forceinline__ long long block_sum_1024(long long v, long long *wsum) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int u = 0; u < 16; ++u) t += wsum[u];
+    __syncthreads();
+    return t;
+}
+
+template <typename V>
+__global__ __launch_bounds__(1024) void scan_reduce_kernel(const V *__restrict__ a, const long long *__restrict__ count,
+                                                          int mult, long long *__restrict__ bsum) {
+    __shared__ long long wsum[16];
+    long long lo, hi;
+    scan_chunk(mult * live_tiles(count[0]), lo, hi);
+    long long s = 0;
+    for (long long i = lo + threadIdx.x; i < hi; i += 1024) s += (long long)a[i];
+    s = block_sum_1024(s, wsum);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+template <typename V>
+__global__ __launch_bounds__(1024) void scan_apply_kernel(V *__restrict__ a, const long long *__restrict__ count, int mult,
+                                                         const long long *__restrict__ bsum, long long *__restrict__ total) {
     __shared__ long long wsum[16];
     __shared__ long long carry;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) carry = 0;
+    long long lo, hi;
+    scan_chunk(mult * live_tiles(count[0]), lo, hi);
+    const long long before = block_sum_1024(tid < (int)blockIdx.x ? bsum[tid] : 0, wsum);
+    if (tid == 0) carry = before;
     __syncthreads();
-    for (int b0 = 0; b0 < nblocks; b0 += 1024) {
-        const int i = b0 + tid;
-        long long v = i < nblocks ? bcounts[i] : 0;
+    for (long long b0 = lo; b0 < hi; b0 += 1024) {
+        const long long i = b0 + tid;
+        const long long v = i < hi ? (long long)a[i] : 0;
         long long inc = v;
         for (int off = 1; off < 64; off <<= 1) {
             const long long o = __shfl_up(inc, off, 64);
@@ -127,7 +172,7 @@ __global__ __launch_bounds__(1024) void pass_scan_kernel(int *__restrict__ bcoun
         __syncthreads();
         long long pre = carry;
         for (int u = 0; u < w; ++u) pre += wsum[u];
-        if (i < nblocks) bcounts[i] = (int)(pre + inc - v);
+        if (i < hi) a[i] = (V)(pre + inc - v);
         __syncthreads();
         if (tid == 0) {
             long long t = 0;
@@ -135,20 +180,25 @@ __global__ __launch_bounds__(1024) void pass_scan_kernel(int *__restrict__ bcoun
             carry += t;
         }
         __syncthreads();
-        if (tid < 16) wsum[tid] = 0;
-        __syncthreads();
     }
-    if (tid == 0) {
-        const long long T = count[0];
-        *updates += (unsigned long long)T * (unsigned long long)ngates;
-        child_base[0] = T;
-        long long nt = T + carry;
-        if (nt > cap2) {
-            count[1] = 1;
-            nt = cap2;
-        }
-        count[0] = nt;
+    if (blockIdx.x == SCAN_BLOCKS - 1 && tid == 0) *total = carry;
+}
+
+// phase 2 tail: appends the children after the live terms, flags overflow,
+// and counts term updates
+__global__ void pass_finalize_kernel(long long *__restrict__ count, const long long *__restrict__ total, long long cap2,
+                                     unsigned long long *__restrict__ updates, int ngates,
+                                     long long *__restrict__ child_base) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const long long T = count[0];
+    *updates += (unsigned long long)T * (unsigned long long)ngates;
+    child_base[0] = T;
+    long long nt = T + *total;
+    if (nt > cap2) {
+        count[1] = 1;
+        nt = cap2;
     }
+    count[0] = nt;
 }
 
 // phase 3: apply the run, rescale parents in place, write children in order
@@ -161,55 +211,58 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_write_kernel(uint64_t *__restri
     __shared__ int wcnt[SP_BLOCK / 64];
     __shared__ int running;
     const long long nlive = child_base[0];
-    const long long b0 = (long long)blockIdx.x * SP_TILE;
-    if (b0 >= nlive) return;
+    const long long L = live_tiles(nlive);
+    if ((long long)blockIdx.x >= L) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double cs = 1.0, sn = 0.0;
     const bool rot = p.rot_op >= 3;
     if (rot) sincos(theta[p.rot_param], &sn, &cs);
-    if (threadIdx.x == 0) running = boffs[blockIdx.x];
-    __syncthreads();
-    for (int it = 0; it < SP_ITEMS; ++it) {
-        const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-        const bool live = i < nlive;
-        uint64_t xx = 0, zz = 0, fx = 0, fz = 0;
-        double cc = 0.0, sg = 1.0;
-        bool anti = false;
-        if (live) {
-            xx = x[i];
-            zz = z[i];
-            cc = ldc<T>(c, i);
-            unsigned neg = 0;
-            clifford_apply(xx, zz, neg, codes, p.g_begin, p.g_end);
-            if (neg) cc = -cc;
-            if (rot) anti = rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg);
-        }
-        const unsigned long long bal = __ballot(anti);
-        const int below = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) wcnt[w] = __popcll(bal);
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        const long long b0 = t * SP_TILE;
+        if (threadIdx.x == 0) running = boffs[t];
         __syncthreads();
-        int off = running;
-        for (int u = 0; u < w; ++u) off += wcnt[u];
-        if (live) {
-            x[i] = xx;
-            z[i] = zz;
-            stc<T>(c, i, anti ? cc * cs : cc);
-            if (anti) {
-                const long long j = nlive + off + below;
-                if (j < cap2) {
-                    x[j] = xx ^ fx;
-                    z[j] = zz ^ fz;
-                    stc<T>(c, j, cc * sg * sn);
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            const long long i = b0 + it * SP_BLOCK + threadIdx.x;
+            const bool live = i < nlive;
+            uint64_t xx = 0, zz = 0, fx = 0, fz = 0;
+            double cc = 0.0, sg = 1.0;
+            bool anti = false;
+            if (live) {
+                xx = x[i];
+                zz = z[i];
+                cc = ldc<T>(c, i);
+                unsigned neg = 0;
+                clifford_apply(xx, zz, neg, codes, p.g_begin, p.g_end);
+                if (neg) cc = -cc;
+                if (rot) anti = rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg);
+            }
+            const unsigned long long bal = __ballot(anti);
+            const int below = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) wcnt[w] = __popcll(bal);
+            __syncthreads();
+            int off = running;
+            for (int u = 0; u < w; ++u) off += wcnt[u];
+            if (live) {
+                x[i] = xx;
+                z[i] = zz;
+                stc<T>(c, i, anti ? cc * cs : cc);
+                if (anti) {
+                    const long long j = nlive + off + below;
+                    if (j < cap2) {
+                        x[j] = xx ^ fx;
+                        z[j] = zz ^ fz;
+                        stc<T>(c, j, cc * sg * sn);
+                    }
                 }
             }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int s = 0;
+                for (int u = 0; u < SP_BLOCK / 64; ++u) s += wcnt[u];
+                running += s;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int t = 0;
-            for (int u = 0; u < SP_BLOCK / 64; ++u) t += wcnt[u];
-            running += t;
-        }
-        __syncthreads();
     }
 }
 
@@ -223,50 +276,25 @@ __device__ __forceinline__ unsigned key_digit(uint64_t x, uint64_t z, int n, int
     return (unsigned)(v & (RADIX - 1));
 }
 
+// Histograms are digit-major over the live tiles: hist[d * L + tile], so an
+// exclusive scan of hist[0, RADIX * L) gives every (digit, tile) its output
+// position.
 __global__ __launch_bounds__(SP_BLOCK) void sort_hist_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z,
                                                             const long long *__restrict__ count, int n, int shift,
-                                                            int ntiles, unsigned *__restrict__ hist) {
+                                                            unsigned *__restrict__ hist) {
     __shared__ unsigned h[RADIX];
-    for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) h[d] = 0;
-    __syncthreads();
     const long long T = count[0];
-    const long long b0 = (long long)blockIdx.x * SP_TILE;
-    for (int it = 0; it < SP_ITEMS; ++it) {
-        const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-        if (i < T) atomicAdd(&h[key_digit(x[i], z[i], n, shift)], 1u);
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) hist[(long long)d * ntiles + blockIdx.x] = h[d];
-}
-
-// exclusive scan over hist[RADIX * ntiles] (digit-major), one workgroup
-__global__ __launch_bounds__(1024) void sort_scan_kernel(unsigned *__restrict__ hist, long long len) {
-    __shared__ long long wsum[16];
-    __shared__ long long carry;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (long long b0 = 0; b0 < len; b0 += 1024) {
-        const long long i = b0 + tid;
-        const long long v = i < len ? hist[i] : 0;
-        long long inc = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long o = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += o;
-        }
-        if (lane == 63) wsum[w] = inc;
+    const long long L = live_tiles(T);
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) h[d] = 0;
         __syncthreads();
-        long long pre = carry;
-        for (int u = 0; u < w; ++u) pre += wsum[u];
-        if (i < len) hist[i] = (unsigned)(pre + inc - v);
-        __syncthreads();
-        if (tid == 0) {
-            long long t = 0;
-            for (int u = 0; u < 16; ++u) t += wsum[u];
-            carry += t;
+        const long long b0 = t * SP_TILE;
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            const long long i = b0 + it * SP_BLOCK + threadIdx.x;
+            if (i < T) atomicAdd(&h[key_digit(x[i], z[i], n, shift)], 1u);
         }
         __syncthreads();
-        if (tid < 16) wsum[tid] = 0;
+        for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) hist[(long long)d * L + t] = h[d];
         __syncthreads();
     }
 }
@@ -282,7 +310,7 @@ __global__ __launch_bounds__(SP_BLOCK) void sort_scatter_kernel(const uint64_t *
                                                                const void *c, uint64_t *__restrict__ xo,
                                                                uint64_t *__restrict__ zo, void *co,
                                                                const long long *__restrict__ count, int n, int shift,
-                                                               int ntiles, const unsigned *__restrict__ hist) {
+                                                               const unsigned *__restrict__ hist) {
     __shared__ unsigned whist[SP_BLOCK / 64][RADIX];
     __shared__ unsigned tpre[RADIX];
     __shared__ unsigned goff[RADIX];
@@ -290,79 +318,82 @@ __global__ __launch_bounds__(SP_BLOCK) void sort_scatter_kernel(const uint64_t *
     __shared__ uint64_t sz[SP_TILE];
     __shared__ T sc[SP_TILE];
     const long long Tn = count[0];
-    const long long b0 = (long long)blockIdx.x * SP_TILE;
-    if (b0 >= Tn) return;
+    const long long L = live_tiles(Tn);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) {
-        for (int v = 0; v < SP_BLOCK / 64; ++v) whist[v][d] = 0;
-        goff[d] = hist[(long long)d * ntiles + blockIdx.x];
-    }
-    __syncthreads();
-
-    uint64_t rx[SP_ITEMS], rz[SP_ITEMS];
-    T rc[SP_ITEMS];
-    unsigned rd[SP_ITEMS], rr[SP_ITEMS];
     const unsigned long long lt = (1ull << lane) - 1ull;
-    for (int j = 0; j < SP_ITEMS; ++j) {
-        const long long i = b0 + (long long)w * (SP_ITEMS * 64) + j * 64 + lane;
-        const bool live = i < Tn;
-        rx[j] = live ? x[i] : 0;
-        rz[j] = live ? z[i] : 0;
-        rc[j] = live ? ((const T *)c)[i] : (T)0;
-        const unsigned d = key_digit(rx[j], rz[j], n, shift);
-        unsigned long long peers = __ballot(live);
-        for (int bt = 0; bt < RADIX_BITS; ++bt) {
-            const unsigned long long bb = __ballot((d >> bt) & 1u);
-            peers &= ((d >> bt) & 1u) ? bb : ~bb;
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        const long long b0 = t * SP_TILE;
+        for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) {
+            for (int v = 0; v < SP_BLOCK / 64; ++v) whist[v][d] = 0;
+            goff[d] = hist[(long long)d * L + t];
         }
-        const unsigned before = whist[w][d];
-        __builtin_amdgcn_wave_barrier();
-        const int rank = __popcll(peers & lt);
-        if (live && rank == 0) whist[w][d] = before + (unsigned)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        rd[j] = live ? d : RADIX;
-        rr[j] = before + (unsigned)rank;
-    }
-    __syncthreads();
-    // per digit: exclusive prefix over waves, then an exclusive scan of the
-    // tile's digit totals (thread d owns digit d; SP_BLOCK == RADIX)
-    {
-        const int d = threadIdx.x;
-        unsigned run = 0;
-        for (int v = 0; v < SP_BLOCK / 64; ++v) {
-            const unsigned cnt = whist[v][d];
-            whist[v][d] = run;
-            run += cnt;
-        }
-        unsigned inc = run;
-        for (int off = 1; off < 64; off <<= 1) {
-            const unsigned o = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += o;
-        }
-        tpre[d] = inc;
         __syncthreads();
-        unsigned add = 0;
-        for (int v = 0; v < w; ++v) add += tpre[v * 64 + 63];
-        __syncthreads();
-        tpre[d] = add + inc - run;
-    }
-    __syncthreads();
-    for (int j = 0; j < SP_ITEMS; ++j) {
-        if (rd[j] < RADIX) {
-            const unsigned pos = tpre[rd[j]] + whist[w][rd[j]] + rr[j];
-            sx[pos] = rx[j];
-            sz[pos] = rz[j];
-            sc[pos] = rc[j];
+
+        uint64_t rx[SP_ITEMS], rz[SP_ITEMS];
+        T rc[SP_ITEMS];
+        unsigned rd[SP_ITEMS], rr[SP_ITEMS];
+        for (int j = 0; j < SP_ITEMS; ++j) {
+            const long long i = b0 + (long long)w * (SP_ITEMS * 64) + j * 64 + lane;
+            const bool live = i < Tn;
+            rx[j] = live ? x[i] : 0;
+            rz[j] = live ? z[i] : 0;
+            rc[j] = live ? ((const T *)c)[i] : (T)0;
+            const unsigned d = key_digit(rx[j], rz[j], n, shift);
+            unsigned long long peers = __ballot(live);
+            for (int bt = 0; bt < RADIX_BITS; ++bt) {
+                const unsigned long long bb = __ballot((d >> bt) & 1u);
+                peers &= ((d >> bt) & 1u) ? bb : ~bb;
+            }
+            const unsigned before = whist[w][d];
+            __builtin_amdgcn_wave_barrier();
+            const int rank = __popcll(peers & lt);
+            if (live && rank == 0) whist[w][d] = before + (unsigned)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+            rd[j] = live ? d : RADIX;
+            rr[j] = before + (unsigned)rank;
         }
-    }
-    __syncthreads();
-    const int valid = (int)((Tn - b0) < SP_TILE ? (Tn - b0) : SP_TILE);
-    for (int i = threadIdx.x; i < valid; i += SP_BLOCK) {
-        const unsigned d = key_digit(sx[i], sz[i], n, shift);
-        const long long g = (long long)goff[d] + (i - (long long)tpre[d]);
-        xo[g] = sx[i];
-        zo[g] = sz[i];
-        ((T *)co)[g] = sc[i];
+        __syncthreads();
+        // per digit: exclusive prefix over waves, then an exclusive scan of the
+        // tile's digit totals (thread d owns digit d; SP_BLOCK == RADIX)
+        {
+            const int d = threadIdx.x;
+            unsigned run = 0;
+            for (int v = 0; v < SP_BLOCK / 64; ++v) {
+                const unsigned cnt = whist[v][d];
+                whist[v][d] = run;
+                run += cnt;
+            }
+            unsigned inc = run;
+            for (int off = 1; off < 64; off <<= 1) {
+                const unsigned o = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += o;
+            }
+            tpre[d] = inc;
+            __syncthreads();
+            unsigned add = 0;
+            for (int v = 0; v < w; ++v) add += tpre[v * 64 + 63];
+            __syncthreads();
+            tpre[d] = add + inc - run;
+        }
+        __syncthreads();
+        for (int j = 0; j < SP_ITEMS; ++j) {
+            if (rd[j] < RADIX) {
+                const unsigned pos = tpre[rd[j]] + whist[w][rd[j]] + rr[j];
+                sx[pos] = rx[j];
+                sz[pos] = rz[j];
+                sc[pos] = rc[j];
+            }
+        }
+        __syncthreads();
+        const int valid = (int)((Tn - b0) < SP_TILE ? (Tn - b0) : SP_TILE);
+        for (int i = threadIdx.x; i < valid; i += SP_BLOCK) {
+            const unsigned d = key_digit(sx[i], sz[i], n, shift);
+            const long long g = (long long)goff[d] + (i - (long long)tpre[d]);
+            xo[g] = sx[i];
+            zo[g] = sz[i];
+            ((T *)co)[g] = sc[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -375,56 +406,32 @@ __global__ __launch_bounds__(SP_BLOCK) void seg_count_kernel(const uint64_t *__r
                                                             const long long *__restrict__ count, int *__restrict__ bcounts) {
     __shared__ int red[SP_BLOCK / 64];
     const long long T = count[0];
-    const long long b0 = (long long)blockIdx.x * SP_TILE;
-    int mine = 0;
-    for (int it = 0; it < SP_ITEMS; ++it) {
-        const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-        if (i < T && seg_head(x, z, i)) ++mine;
-    }
-    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mine;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < SP_BLOCK / 64; ++w) t += red[w];
-        bcounts[blockIdx.x] = t;
+    const long long L = live_tiles(T);
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        const long long b0 = t * SP_TILE;
+        int mine = 0;
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            const long long i = b0 + it * SP_BLOCK + threadIdx.x;
+            if (i < T && seg_head(x, z, i)) ++mine;
+        }
+        for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int s = 0;
+            for (int w = 0; w < SP_BLOCK / 64; ++w) s += red[w];
+            bcounts[t] = s;
+        }
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(1024) void seg_scan_kernel(int *__restrict__ bcounts, int nblocks, long long *__restrict__ count,
-                                                       long long *__restrict__ old_count) {
-    __shared__ long long wsum[16];
-    __shared__ long long carry;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int b0 = 0; b0 < nblocks; b0 += 1024) {
-        const int i = b0 + tid;
-        long long v = i < nblocks ? bcounts[i] : 0;
-        long long inc = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long o = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += o;
-        }
-        if (lane == 63) wsum[w] = inc;
-        __syncthreads();
-        long long pre = carry;
-        for (int u = 0; u < w; ++u) pre += wsum[u];
-        if (i < nblocks) bcounts[i] = (int)(pre + inc - v);
-        __syncthreads();
-        if (tid == 0) {
-            long long t = 0;
-            for (int u = 0; u < 16; ++u) t += wsum[u];
-            carry += t;
-        }
-        __syncthreads();
-        if (tid < 16) wsum[tid] = 0;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        old_count[0] = count[0];
-        count[0] = carry;
-    }
+// the merged count replaces the live count; the old one stays for the write
+__global__ void seg_finalize_kernel(long long *__restrict__ count, const long long *__restrict__ total,
+                                    long long *__restrict__ old_count) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    old_count[0] = count[0];
+    count[0] = *total;
 }
 
 template <typename T>
@@ -436,35 +443,37 @@ __global__ __launch_bounds__(SP_BLOCK) void seg_write_kernel(const uint64_t *__r
     __shared__ int wcnt[SP_BLOCK / 64];
     __shared__ int running;
     const long long nlive = old_count[0];
-    const long long b0 = (long long)blockIdx.x * SP_TILE;
-    if (b0 >= nlive) return;
+    const long long L = live_tiles(nlive);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) running = boffs[blockIdx.x];
-    __syncthreads();
-    for (int it = 0; it < SP_ITEMS; ++it) {
-        const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-        const bool head = i < nlive && seg_head(x, z, i);
-        const unsigned long long bal = __ballot(head);
-        const int below = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) wcnt[w] = __popcll(bal);
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        const long long b0 = t * SP_TILE;
+        if (threadIdx.x == 0) running = boffs[t];
         __syncthreads();
-        int off = running;
-        for (int u = 0; u < w; ++u) off += wcnt[u];
-        if (head) {
-            double s = ldc<T>(c, i);
-            for (long long j = i + 1; j < nlive && x[j] == x[i] && z[j] == z[i]; ++j) s += ldc<T>(c, j);
-            const long long o = off + below;
-            xo[o] = x[i];
-            zo[o] = z[i];
-            stc<T>(co, o, s);
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            const long long i = b0 + it * SP_BLOCK + threadIdx.x;
+            const bool head = i < nlive && seg_head(x, z, i);
+            const unsigned long long bal = __ballot(head);
+            const int below = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) wcnt[w] = __popcll(bal);
+            __syncthreads();
+            int off = running;
+            for (int u = 0; u < w; ++u) off += wcnt[u];
+            if (head) {
+                double s = ldc<T>(c, i);
+                for (long long j = i + 1; j < nlive && x[j] == x[i] && z[j] == z[i]; ++j) s += ldc<T>(c, j);
+                const long long o = off + below;
+                xo[o] = x[i];
+                zo[o] = z[i];
+                stc<T>(co, o, s);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int s = 0;
+                for (int u = 0; u < SP_BLOCK / 64; ++u) s += wcnt[u];
+                running += s;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int t = 0;
-            for (int u = 0; u < SP_BLOCK / 64; ++u) t += wcnt[u];
-            running += t;
-        }
-        __syncthreads();
     }
 }
 
@@ -512,7 +521,17 @@ __global__ void sp_init_kernel(uint64_t *x, uint64_t *z, void *c, long long *cou
 }
 
 // ------------------------------------------------------------ launchers
-static int tiles_for(long long cap2) { return (int)((cap2 + SP_TILE - 1) / SP_TILE); }
+// grid of a tile kernel: the capacity's tiles, at most SP_GRID workgroups
+static int grid_for(const SparseBuffers &b) {
+    const long long tiles = (b.cap2 + SP_TILE - 1) / SP_TILE;
+    return (int)std::max<long long>(1, std::min<long long>(tiles, SP_GRID));
+}
+
+template <typename V>
+static void launch_scan(V *a, const long long *count, int mult, SparseBuffers &b, long long *total, hipStream_t s) {
+    hipLaunchKernelGGL(scan_reduce_kernel<V>, dim3(SCAN_BLOCKS), dim3(1024), 0, s, a, count, mult, b.scan);
+    hipLaunchKernelGGL(scan_apply_kernel<V>, dim3(SCAN_BLOCKS), dim3(1024), 0, s, a, count, mult, b.scan, total);
+}
 
 hipError_t launch_sparse_init(SparseBuffers &b, int dtype_bytes, const uint64_t *x, const uint64_t *z,
                               const double *c, int nterms, hipStream_t s) {
@@ -527,47 +546,48 @@ hipError_t launch_sparse_init(SparseBuffers &b, int dtype_bytes, const uint64_t 
 
 hipError_t launch_sparse_pass(SparseBuffers &b, int dtype_bytes, const uint32_t *codes, const SparsePassDesc &p,
                               const double *theta, hipStream_t s) {
-    // the grid covers the whole capacity; blocks past the live count exit
-    const int nt = tiles_for(b.cap2);
+    const int g = grid_for(b);
     int *bc = b.tile_flags;
-    long long *child_base = b.count + 2;
-    hipLaunchKernelGGL(pass_count_kernel, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, codes, p, bc);
-    hipLaunchKernelGGL(pass_scan_kernel, dim3(1), dim3(1024), 0, s, bc, nt, b.count, b.cap2, b.updates, p.ngates,
+    long long *child_base = b.count + 2, *total = b.count + 4;
+    hipLaunchKernelGGL(pass_count_kernel, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, codes, p, bc);
+    launch_scan<int>(bc, b.count, 1, b, total, s);
+    hipLaunchKernelGGL(pass_finalize_kernel, dim3(1), dim3(64), 0, s, b.count, total, b.cap2, b.updates, p.ngates,
                        child_base);
     if (dtype_bytes == 8)
-        hipLaunchKernelGGL(pass_write_kernel<double>, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, child_base,
-                           b.cap2, codes, p, theta, bc);
+        hipLaunchKernelGGL(pass_write_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, child_base, b.cap2,
+                           codes, p, theta, bc);
     else
-        hipLaunchKernelGGL(pass_write_kernel<float>, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, child_base, b.cap2,
+        hipLaunchKernelGGL(pass_write_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, child_base, b.cap2,
                            codes, p, theta, bc);
     return hipGetLastError();
 }
 
 hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStream_t s) {
-    const int nt = tiles_for(b.cap2);
+    const int g = grid_for(b);
     const int key_bits = 2 * n;
+    long long *old_count = b.count + 3, *total = b.count + 4;
     for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
-        hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, n, shift, nt, b.hist);
-        hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, s, b.hist, (long long)RADIX * nt);
+        hipLaunchKernelGGL(sort_hist_kernel, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, n, shift, b.hist);
+        launch_scan<unsigned>(b.hist, b.count, RADIX, b, total, s);
         if (dtype_bytes == 8)
-            hipLaunchKernelGGL(sort_scatter_kernel<double>, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2,
-                               b.c2, b.count, n, shift, nt, b.hist);
+            hipLaunchKernelGGL(sort_scatter_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2,
+                               b.c2, b.count, n, shift, b.hist);
         else
-            hipLaunchKernelGGL(sort_scatter_kernel<float>, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2,
-                               b.c2, b.count, n, shift, nt, b.hist);
+            hipLaunchKernelGGL(sort_scatter_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2,
+                               b.c2, b.count, n, shift, b.hist);
         std::swap(b.x, b.x2);
         std::swap(b.z, b.z2);
         std::swap(b.c, b.c2);
     }
     int *bc = b.tile_flags;
-    long long *old_count = b.count + 3;
-    hipLaunchKernelGGL(seg_count_kernel, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, bc);
-    hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, bc, nt, b.count, old_count);
+    hipLaunchKernelGGL(seg_count_kernel, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, bc);
+    launch_scan<int>(bc, b.count, 1, b, total, s);
+    hipLaunchKernelGGL(seg_finalize_kernel, dim3(1), dim3(64), 0, s, b.count, total, old_count);
     if (dtype_bytes == 8)
-        hipLaunchKernelGGL(seg_write_kernel<double>, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2, b.c2,
+        hipLaunchKernelGGL(seg_write_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2, b.c2,
                            old_count, bc);
     else
-        hipLaunchKernelGGL(seg_write_kernel<float>, dim3(nt), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2, b.c2,
+        hipLaunchKernelGGL(seg_write_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2, b.c2,
                            old_count, bc);
     std::swap(b.x, b.x2);
     std::swap(b.z, b.z2);

@@ -247,6 +247,37 @@ def chain_zxz_circuit(seed=6, n=4, layers=50, repeats=100):
     return make_circuit(n, gates, p, obs_z(n, [0]), theta, name=f"chainzxz{n}x{layers}x{repeats}")
 
 
+def spread_circuit(seed, n, k):
+    """A circuit whose Heisenberg string set has a known size, for sets of
+    millions of strings.  In application order: H on every even qubit, S on
+    every qubit divisible by 3, a CX chain 0->1, ..., (n-2)->(n-1); then RY on
+    qubits 0..k-1; then RX on every qubit.  O = Z^n.
+
+    Propagated backward, the RX layer turns Z^n into all 2^n strings over
+    {Z, Y}; each RY sends Z to {Z, X} and keeps Y, giving 2^(n-k) 3^k strings;
+    the Clifford prefix maps strings one to one.  meta["final_terms"] holds
+    that count."""
+    rng = np.random.default_rng(seed)
+    ops, q0s, q1s, params = [], [], [], []
+    for q in range(0, n, 2):
+        ops.append(H); q0s.append(q); q1s.append(-1); params.append(-1)
+    for q in range(0, n, 3):
+        ops.append(S); q0s.append(q); q1s.append(-1); params.append(-1)
+    for q in range(n - 1):
+        ops.append(CX); q0s.append(q); q1s.append(q + 1); params.append(-1)
+    p = 0
+    for q in range(k):
+        ops.append(RY); q0s.append(q); q1s.append(-1); params.append(p)
+        p += 1
+    for q in range(n):
+        ops.append(RX); q0s.append(q); q1s.append(-1); params.append(p)
+        p += 1
+    theta = rng.uniform(0.0, TWO_PI, size=p)
+    obs = observable([(0, (1 << n) - 1, 1.0)])
+    return make_circuit(n, _arrays(ops, q0s, q1s, params), p, obs, theta, name=f"spread{n}k{k}",
+                        meta={"final_terms": (2 ** (n - k)) * (3 ** k)})
+
+
 # ---------------------------------------------------------- the five workloads
 def config1(seed=1):
     """n=4, HEA-10 (160 gates), O = Z_0, FP64."""

@@ -21,3 +21,14 @@ def test_configs_are_seeded_and_reproducible():
     for x, y in zip(a, b):
         assert np.array_equal(x.op, y.op) and np.array_equal(x.theta, y.theta)
     assert W.config1().m == 160 and W.config4().n_params == 960
+
+
+def test_spread_circuit_set_size_is_the_closed_form():
+    """The oracle's final set of the spread circuit has 2^(n-k) 3^k strings and
+    its <O> is the state vector's."""
+    import oracle
+    for n, k in ((6, 0), (6, 2), (8, 3), (9, 9)):
+        w = W.spread_circuit(n + k, n, k)
+        r = oracle.propagate(w)
+        assert len(r.x) == w.meta["final_terms"] == 2 ** (n - k) * 3 ** k
+        assert abs(r.expval - oracle.expval_sv(w)) <= 1e-12
