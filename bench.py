@@ -235,6 +235,33 @@ def gradient_leg(api, torch):
             "max_abs_adjoint_minus_psr": float(np.max(np.abs(g_adj.cpu().numpy() - g_psr)))}
 
 
+def sparse_leg(api, torch):
+    """The sort-merge engine past the dense range (n = 20, 4^n slots): a seeded
+    300-gate random circuit (2.66M strings at the end) and the spread circuit
+    (n = 20, RY on 5 qubits: 7,962,624 strings), one evaluation each timed."""
+    from paper_2502_10685_amd import workloads as W
+    cases = [("random n=20 m=300 seed 20", W.random_circuit(np.random.default_rng(20), 20, 300, W.obs_z(20, [0, 1]))),
+             ("spread n=20 k=5", W.spread_circuit(20, 20, 5))]
+    out = []
+    for name, wc in cases:
+        c = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 24)
+        c.evaluate()
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ev = c.evaluate()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        st = c.stats()
+        out.append({"workload": name, "gates": wc.m, "ms": dt * 1e3, "final_terms": int(st["final_terms"]),
+                    "term_updates": int(st["term_updates"]), "passes": int(st["passes"]),
+                    "updates_per_s": st["term_updates"] / dt, "overflow": bool(st["overflow"]),
+                    "expval": float(ev.item())})
+        c.close()
+    return out
+
+
 def cpu_baseline(circs, gpu_vals, seconds, updates):
     """The oracle's scalar propagator on a bounded sample of the workload: every
     8th circuit whose estimated cost still fits the time budget."""
@@ -279,6 +306,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sort-merge engine leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
                     help="time the tuning candidates on this device first (defaults are MI355X measurements)")
@@ -433,6 +461,13 @@ def main():
         res["gradient"] = gradient_leg(api, torch)
         log(f"gradient: adjoint {res['gradient']['adjoint_ms']:.2f} ms, psr sweep "
             f"{res['gradient']['psr_sweep_ms']:.2f} ms")
+
+    if not args.no_sparse and args.workload == "batch512":
+        log("sparse engine: n = 20")
+        res["sparse"] = sparse_leg(api, torch)
+        for r in res["sparse"]:
+            log(f"sparse {r['workload']}: {r['ms']:.2f} ms, {r['final_terms']} strings, "
+                f"{r['updates_per_s']:.3e} updates/s")
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -329,16 +329,40 @@ __device__ __forceinline__ void u1_regs(double *v, const double *M) {
 // Ops and their maps are staged through LDS in chunks: one cooperative load
 // per chunk instead of a dependent global load per op.
 constexpr int OPCH = 32;
-struct OpCache {
-    DOp ops[OPCH];
-    double maps[OPCH][9];
+template <int CH>
+struct OpCacheN {
+    DOp ops[CH];
+    double maps[CH][9];
 };
+using OpCache = OpCacheN<OPCH>;
+
+// Stages ops [o0, o0 + cn) and the maps of their U1 ops into an op cache.
+// Ops move as raw 16-byte words from the global address space: copied as a
+// struct of bytes they would go through scratch, whose wait covers every
+// outstanding vector load (tile prefetches included).
+template <int CH>
+__device__ __forceinline__ void stage_ops(OpCacheN<CH> *oc, const DOp *ops, const double *maps, int o0, int cn, int tid,
+                                          int nthreads) {
+    typedef unsigned U4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) U4 *GOps;
+    typedef const __attribute__((address_space(1))) double *GMaps;
+    for (int j = tid; j < cn; j += nthreads) {
+        const U4 w = ((GOps)ops)[o0 + j];
+        reinterpret_cast<U4 *>(oc->ops)[j] = w;
+        if ((w.x & 0xffu) == DOP_U1) {
+            const GMaps src = (GMaps)maps + 9ull * w.z;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) oc->maps[j][k] = src[k];
+        }
+    }
+}
 
 // A GROUP of cnt ops on digits a < b: each thread owns whole 16-slot blocks
 // (all letters of the two digits), applies every member op in registers and
 // writes the block back once.
 template <typename T, int K, int BLOCK>
-__device__ __forceinline__ void group_apply(T *lc, int a, int b, const OpCache *oc, int first, int cnt, int tid) {
+__device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, const double (*maps)[9], int first,
+                                            int cnt, int tid) {
     constexpr int NG = 1 << (2 * (K - 2));
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
     if (NG < BLOCK && tid >= NG) return;
@@ -354,11 +378,11 @@ __device__ __forceinline__ void group_apply(T *lc, int a, int b, const OpCache *
         for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * a)) | ((e >> 2) << (2 * b)))];
 #pragma unroll 1
         for (int t = first; t < first + cnt; ++t) {
-            const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[t])[0]);
+            const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&ops[t])[0]);
             const int kind = w0 & 0xff, da = (w0 >> 8) & 0xff;
             if (kind == DOP_U1) {
-                if (da == a) u1_regs<true>(v, oc->maps[t]);
-                else u1_regs<false>(v, oc->maps[t]);
+                if (da == a) u1_regs<true>(v, maps[t]);
+                else u1_regs<false>(v, maps[t]);
             } else {
                 if (da == a) cx_regs<true>(v);
                 else cx_regs<false>(v);
@@ -372,24 +396,16 @@ __device__ __forceinline__ void group_apply(T *lc, int a, int b, const OpCache *
 // Applies ops [o0, o1) to an LDS tile of 4^K slots.  For tracked runs it
 // accumulates term updates: every op adds ngates * (strings in the tile
 // before it), and U1 ops that can create strings update that count.
-template <typename T, bool TRACK, int K, int BLOCK>
+template <typename T, bool TRACK, int K, int BLOCK, int CH = OPCH>
 __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const double *__restrict__ maps, int o0,
-                        int o1, long long &tcount, long long &updates, long long *redi, OpCache *oc,
+                        int o1, long long &tcount, long long &updates, long long *redi, OpCacheN<CH> *oc,
                         bool preloaded = false) {
     const int tid = threadIdx.x;
     int cb = o0;
     while (cb < o1) {
-        const int cn = (o1 - cb) < OPCH ? (o1 - cb) : OPCH;
+        const int cn = (o1 - cb) < CH ? (o1 - cb) : CH;
         lds_barrier();
-        if (!preloaded && tid < cn) {
-            const DOp op = ops[cb + tid];
-            oc->ops[tid] = op;
-            if (op.kind == DOP_U1) {
-                const double *src = maps + 9ull * op.map;
-#pragma unroll
-                for (int j = 0; j < 9; ++j) oc->maps[tid][j] = src[j];
-            }
-        }
+        if (!preloaded) stage_ops<CH>(oc, ops, maps, cb, cn, tid, BLOCK);
         lds_barrier();
         preloaded = false;
         int i = 0;
@@ -405,7 +421,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
             }
             if (kind == DOP_GROUP) {
                 if (i + 1 + ngates > cn) break;  // reload the chunk from this header
-                if constexpr (K >= 2) group_apply<T, K, BLOCK>(lc, a, b, oc, i + 1, ngates, tid);
+                if constexpr (K >= 2) group_apply<T, K, BLOCK>(lc, a, b, oc->ops, oc->maps, i + 1, ngates, tid);
                 i += 1 + ngates;
             } else if (kind == DOP_U1) {
                 const int delta = u1_apply<T, TRACK, K, BLOCK>(lc, lp, a, oc->maps[i], smask, tid);
@@ -638,6 +654,10 @@ constexpr int kStreamBlock = K >= 7 ? 512 : 256;
 template <int K>
 constexpr int kStreamWaves = K >= 7 ? 2 : 3;
 
+// ops held per workgroup: every 6-qubit pass of the planner fits (its passes
+// have at most 64 op entries); longer passes reload chunks inside run_ops
+constexpr int kStreamOps = 64;
+
 template <typename T, int K>
 __global__ __launch_bounds__(kStreamBlock<K>) __attribute__((amdgpu_waves_per_eu(kStreamWaves<K>)))
 void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) {
@@ -647,10 +667,14 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
     static_assert(K >= 4, "the thread index supplies four digits");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long redi[BLOCK / 64];
-    __shared__ OpCache oc;
+    __shared__ OpCacheN<kStreamOps> oc;
     T *lc = reinterpret_cast<T *>(smem);
     const int tid = threadIdx.x;
     const int stid = sw(tid);
+    // tiles with stride gridDim.x: the co-resident workgroups work on
+    // neighbouring tiles at any moment, and neighbouring tiles interleave in
+    // memory (at 128-byte granularity when the tile holds qubits 0 and 1), so
+    // their loads and stores share DRAM pages
     const int total = grp.first_block[grp.ngroups];
     int blk = blockIdx.x;
     if (blk >= total) return;
@@ -661,24 +685,20 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
         const uint64_t qubits = cur.d->qubits;
 #pragma unroll
         for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, cur.voff, stream_soff<T, K, BLOCK>(qubits, r));
-    }
-    long long tcount = 0, updates = 0;
-    for (;;) {
-        lds_barrier();  // the previous tile's LDS reads are done
 #pragma unroll
         for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
+    }
+    // Per tile: ops (unless the descriptor repeats), the next tile's loads,
+    // the ops in LDS, then this tile's stores are issued before the wait for
+    // the next tile's loads, so neither wait covers fresh stores.
+    const TilePassDesc *cached = nullptr;  // descriptor whose whole op list is in oc
+    long long tcount = 0, updates = 0;
+    for (;;) {
         const int o0 = cur.d->op_begin, o1 = cur.d->op_end;
-        const int cn = (o1 - o0) < OPCH ? (o1 - o0) : OPCH;
-        // first op chunk of this tile, then the next tile's prefetch
-        DOp opr{};
-        double mr[9];
-        if (tid < cn) {
-            opr = cur.d->ops[o0 + tid];
-            if (opr.kind == DOP_U1) {
-                const double *src = cur.d->maps + 9ull * opr.map;
-#pragma unroll
-                for (int j = 0; j < 9; ++j) mr[j] = src[j];
-            }
+        const bool fits = o1 - o0 <= kStreamOps;
+        if (cur.d != cached) {
+            stage_ops<kStreamOps>(&oc, cur.d->ops, cur.d->maps, o0, fits ? o1 - o0 : kStreamOps, tid, BLOCK);
+            cached = fits ? cur.d : nullptr;
         }
         const int nblk = blk + gridDim.x;
         const bool has_next = nblk < total;
@@ -690,21 +710,22 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
 #pragma unroll
             for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
         }
-        if (tid < cn) {
-            oc.ops[tid] = opr;
-            if (opr.kind == DOP_U1) {
+        run_ops<T, false, K, BLOCK, kStreamOps>(lc, nullptr, cur.d->ops, cur.d->maps, o0, o1, tcount, updates, redi, &oc,
+                                                true);
+        if (!fits) cached = nullptr;  // run_ops reloaded later chunks into oc
+        T out[PER];
 #pragma unroll
-                for (int j = 0; j < 9; ++j) oc.maps[tid][j] = mr[j];
-            }
-        }
-        run_ops<T, false, K, BLOCK>(lc, nullptr, cur.d->ops, cur.d->maps, o0, o1, tcount, updates, redi, &oc, true);
+        for (int r = 0; r < PER; ++r) out[r] = lc[stid ^ sw(r * BLOCK)];
         {
             const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(cur.d->coef) + cur.base);
             const uint64_t qubits = cur.d->qubits;
 #pragma unroll
-            for (int r = 0; r < PER; ++r) BufIO<T>::st(rs, cur.voff, stream_soff<T, K, BLOCK>(qubits, r), lc[stid ^ sw(r * BLOCK)]);
+            for (int r = 0; r < PER; ++r) BufIO<T>::st(rs, cur.voff, stream_soff<T, K, BLOCK>(qubits, r), out[r]);
         }
         if (!has_next) break;
+        lds_barrier();  // every thread has read this tile and is done with oc
+#pragma unroll
+        for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
         blk = nblk;
         cur = nxt;
     }
@@ -1133,15 +1154,7 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const GradPassDesc *__restr
     for (int cb = d.op_begin; cb < d.op_end; cb += OPCH) {
         const int cn = (d.op_end - cb) < OPCH ? (d.op_end - cb) : OPCH;
         lds_barrier();
-        if (tid < cn) {
-            const DOp op = d.ops[cb + tid];
-            oc.ops[tid] = op;
-            if (op.kind == DOP_U1) {
-                const double *src = d.maps + 9ull * op.map;
-#pragma unroll
-                for (int j = 0; j < 9; ++j) oc.maps[tid][j] = src[j];
-            }
-        }
+        stage_ops<OPCH>(&oc, d.ops, d.maps, cb, cn, tid, BLOCK);
         lds_barrier();
         for (int i = 0; i < cn; ++i) {
             const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc.ops[i])[0]);
