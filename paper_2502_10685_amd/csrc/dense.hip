@@ -27,16 +27,16 @@
 
 namespace pp {
 
-// Bank swizzle for 8-byte LDS words: XOR the low 4 index bits with a
-// function of bits 4-5.  It keeps every 16-slot block in place (so tiles
-// smaller than 16 slots are unaffected) and spreads the three access
-// patterns used below (quads on digit 0, on digit 1, and on digits >= 2)
-// over distinct banks.
-__device__ __forceinline__ int sw(int i) { return i ^ (((i >> 4) & 3) * 5); }
+// Bank swizzle for 8-byte LDS words.  The LDS has 64 four-byte banks and
+// serves a 64-bit read or write per half-wave, so a half-wave is free of
+// conflicts when its 32 slot indices are distinct modulo 32.  The swizzle
+// XORs index bits 0-4 with bits 5-9 and with bits 7-11: it is linear over
+// GF(2), keeps every 32-slot block's set of high bits, and (with the lane
+// order that group_sweep picks per digit pair) lets every digit pair of 5-,
+// 6- and 7-digit tiles be swept without conflicts.
+__host__ __device__ constexpr int sw(int i) { return i ^ ((i >> 5) & 31) ^ ((i >> 7) & 31); }
 
-// For i = base | off with disjoint bits, sw(i) = sw(base) ^ sw(off): bits 4-5
-// of i are the disjoint union of those of base and off, and 5 * (p | q) =
-// 5p ^ 5q for disjoint two-bit p, q.  Slot offsets of an op's letters are
+// sw(base ^ off) = sw(base) ^ sw(off): slot offsets of an op's letters are
 // the same for every lane, so each address costs one XOR with a uniform.
 
 // Workgroup barrier for LDS data: the fences are scoped to LDS, so global
@@ -357,40 +357,122 @@ __device__ __forceinline__ void stage_ops(OpCacheN<CH> *oc, const DOp *ops, cons
     }
 }
 
-// A GROUP of cnt ops on digits a < b: each thread owns whole 16-slot blocks
+// Lane order of a group sweep on digits (A, B) of a 4^K-slot tile: thread u
+// owns the 16-slot block whose other digits are u's bits deposited at
+// pos[0..2(K-2)).  The first five positions are the first five free index
+// bits (in lexicographic order of their positions) whose images under sw
+// are independent modulo 32, so the 32 lanes of a half-wave hit 32
+// distinct bank pairs; the other free bits follow in ascending order.
+struct LaneOrder {
+    int pos[14];
+};
+constexpr int gf2_rank(int *v, int n) {
+    int r = 0;
+    for (int bit = 0; bit < 5; ++bit) {
+        int piv = -1;
+        for (int i = r; i < n; ++i)
+            if ((v[i] >> bit) & 1) {
+                piv = i;
+                break;
+            }
+        if (piv < 0) continue;
+        const int t = v[r];
+        v[r] = v[piv];
+        v[piv] = t;
+        for (int i = 0; i < n; ++i)
+            if (i != r && ((v[i] >> bit) & 1)) v[i] ^= v[r];
+        ++r;
+    }
+    return r;
+}
+template <int K, int A, int B>
+constexpr LaneOrder lane_order() {
+    int fr[14] = {0};
+    int nf = 0;
+    for (int d = 0; d < K; ++d)
+        if (d != A && d != B) {
+            fr[nf++] = 2 * d;
+            fr[nf++] = 2 * d + 1;
+        }
+    LaneOrder o{};
+    for (int j = 0; j < nf; ++j) o.pos[j] = fr[j];
+    if (nf < 5) return o;
+    for (int i0 = 0; i0 < nf; ++i0)
+        for (int i1 = i0 + 1; i1 < nf; ++i1)
+            for (int i2 = i1 + 1; i2 < nf; ++i2)
+                for (int i3 = i2 + 1; i3 < nf; ++i3)
+                    for (int i4 = i3 + 1; i4 < nf; ++i4) {
+                        const int idx[5] = {i0, i1, i2, i3, i4};
+                        int c[5] = {0};
+                        for (int k = 0; k < 5; ++k) c[k] = sw(1 << fr[idx[k]]) & 31;
+                        if (gf2_rank(c, 5) < 5) continue;
+                        int j = 0;
+                        for (int k = 0; k < 5; ++k) o.pos[j++] = fr[idx[k]];
+                        for (int f = 0; f < nf; ++f)
+                            if (f != i0 && f != i1 && f != i2 && f != i3 && f != i4) o.pos[j++] = fr[f];
+                        return o;
+                    }
+    return o;
+}
+
+// A GROUP of cnt ops on digits A < B: each thread owns whole 16-slot blocks
 // (all letters of the two digits), applies every member op in registers and
-// writes the block back once.
-template <typename T, int K, int BLOCK>
-__device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, const double (*maps)[9], int first,
-                                            int cnt, int tid) {
+// writes the block back once.  Compiled per digit pair, so the sixteen
+// letter offsets are constants.
+template <typename T, int K, int BLOCK, int A, int B>
+__device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double (*maps)[9], int first, int cnt,
+                                            int tid) {
     constexpr int NG = 1 << (2 * (K - 2));
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
+    constexpr LaneOrder lo = lane_order<K, A, B>();
     if (NG < BLOCK && tid >= NG) return;
-    const int mlo = (1 << (2 * a)) - 1, mhi = (1 << (2 * b)) - 1;
 #pragma unroll 1
     for (int j = 0; j < GPT; ++j) {
-        const int u = tid + j * BLOCK;
-        int v0 = ((u & ~mlo) << 2) | (u & mlo);
-        v0 = ((v0 & ~mhi) << 2) | (v0 & mhi);
+        int u = tid + j * BLOCK;
+        // the addresses below are loop invariant for every digit pair; an
+        // opaque u keeps the compiler from hoisting all pairs' addresses out
+        // of the tile loop (they would not fit in registers)
+        __asm__ volatile("" : "+v"(u));
+        int v0 = 0;
+#pragma unroll
+        for (int q = 0; q < 2 * (K - 2); ++q) v0 |= ((u >> q) & 1) << lo.pos[q];
         const int sv = sw(v0);
         double v[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * a)) | ((e >> 2) << (2 * b)))];
+        for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))];
 #pragma unroll 1
         for (int t = first; t < first + cnt; ++t) {
             const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&ops[t])[0]);
             const int kind = w0 & 0xff, da = (w0 >> 8) & 0xff;
             if (kind == DOP_U1) {
-                if (da == a) u1_regs<true>(v, maps[t]);
+                if (da == A) u1_regs<true>(v, maps[t]);
                 else u1_regs<false>(v, maps[t]);
             } else {
-                if (da == a) cx_regs<true>(v);
+                if (da == A) cx_regs<true>(v);
                 else cx_regs<false>(v);
             }
         }
 #pragma unroll
-        for (int e = 0; e < 16; ++e) lc[sv ^ sw(((e & 3) << (2 * a)) | ((e >> 2) << (2 * b)))] = (T)v[e];
+        for (int e = 0; e < 16; ++e) lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))] = (T)v[e];
     }
+}
+
+template <typename T, int K, int BLOCK>
+__device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, const double (*maps)[9], int first,
+                                            int cnt, int tid) {
+#define PP_GROUP_CASE(A_, B_)                                                               \
+    case (A_) * 8 + (B_):                                                                  \
+        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, maps, first, cnt, tid); \
+        return;
+    switch (a * 8 + b) {
+        PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
+        PP_GROUP_CASE(0, 6) PP_GROUP_CASE(1, 2) PP_GROUP_CASE(1, 3) PP_GROUP_CASE(1, 4) PP_GROUP_CASE(1, 5)
+        PP_GROUP_CASE(1, 6) PP_GROUP_CASE(2, 3) PP_GROUP_CASE(2, 4) PP_GROUP_CASE(2, 5) PP_GROUP_CASE(2, 6)
+        PP_GROUP_CASE(3, 4) PP_GROUP_CASE(3, 5) PP_GROUP_CASE(3, 6) PP_GROUP_CASE(4, 5) PP_GROUP_CASE(4, 6)
+        PP_GROUP_CASE(5, 6)
+    default: return;  // the planner emits GROUP headers with a < b < K only
+    }
+#undef PP_GROUP_CASE
 }
 
 // Applies ops [o0, o1) to an LDS tile of 4^K slots.  For tracked runs it
