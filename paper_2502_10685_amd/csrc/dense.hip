@@ -505,6 +505,15 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
                 if (i + 1 + ngates > cn) break;  // reload the chunk from this header
                 if constexpr (K >= 2) group_apply<T, K, BLOCK>(lc, a, b, oc->ops, oc->maps, i + 1, ngates, tid);
                 i += 1 + ngates;
+            } else if (!TRACK && K >= 2 && K <= 7) {
+                // untracked U1 or CX alone: a group sweep of one op over its
+                // digit pair (a U1 borrows a neighbouring digit), which keeps
+                // the conflict-free lane order of the pair
+                const int other = kind == DOP_U1 ? (a == 0 ? 1 : a - 1) : b;
+                if constexpr (K >= 2)
+                    group_apply<T, K, BLOCK>(lc, a < other ? a : other, a < other ? other : a, oc->ops, oc->maps, i, 1,
+                                             tid);
+                ++i;
             } else if (kind == DOP_U1) {
                 const int delta = u1_apply<T, TRACK, K, BLOCK>(lc, lp, a, oc->maps[i], smask, tid);
                 if (TRACK) {
