@@ -437,16 +437,25 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double 
 #pragma unroll
         for (int q = 0; q < 2 * (K - 2); ++q) v0 |= ((u >> q) & 1) << lo.pos[q];
         const int sv = sw(v0);
+        // word 0 of member t sits in lane t (cnt <= kMaxGroupOps < 64): one LDS
+        // read issued with the block's reads instead of a round trip per
+        // member.  Only when every lane of the wave takes part (NG >= 64);
+        // smaller tiles read each member's word on its own.
+        const int lane = tid & 63;
+        uint32_t wl = 0;
+        if constexpr (NG >= 64) wl = reinterpret_cast<const uint32_t *>(&ops[first + (lane < cnt ? lane : 0)])[0];
         double v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))];
 #pragma unroll 1
-        for (int t = first; t < first + cnt; ++t) {
-            const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&ops[t])[0]);
+        for (int t = 0; t < cnt; ++t) {
+            const uint32_t w0 = NG >= 64
+                                    ? __builtin_amdgcn_readlane(wl, t)
+                                    : __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&ops[first + t])[0]);
             const int kind = w0 & 0xff, da = (w0 >> 8) & 0xff;
             if (kind == DOP_U1) {
-                if (da == A) u1_regs<true>(v, maps[t]);
-                else u1_regs<false>(v, maps[t]);
+                if (da == A) u1_regs<true>(v, maps[first + t]);
+                else u1_regs<false>(v, maps[first + t]);
             } else {
                 if (da == A) cx_regs<true>(v);
                 else cx_regs<false>(v);
