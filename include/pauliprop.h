@@ -188,6 +188,20 @@ PP_API pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const double *
 PP_API pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_every_gates, double *d_expval,
                       double *d_grad);
 
+/* Density matrix rho = U(theta) |0...0><0...0| U(theta)^dag (the paper's toDM
+ * task; density operator as a sum over the stabilizer group, eq. (3), decoded
+ * as in Sec. III-D).  The 2^n group strings Z^z are propagated through the
+ * circuit in the Schrodinger picture on the DENSE engine (an internal circuit
+ * of the inverse gates, built on the first call after pp_circuit_load_gates;
+ * its 4^n weights stay allocated with c), then a Walsh-Hadamard transform per
+ * X part turns the Pauli weights into matrix entries.  d_rho: caller-owned
+ * device memory of 2 * 4^n doubles, row-major complex (real, imaginary)
+ * pairs, rho[a][b] at 2 * (a * 2^n + b); bit q of a basis index is qubit q.
+ * Uses the gates and theta of c (not its observable); the weight type follows
+ * c's dtype, the decode is FP64.  n <= 12 (PP_ERR_INVALID above), PP_ERR_STATE
+ * without gates or theta.  Enqueued on `stream`. */
+PP_API pp_status pp_density_matrix(pp_circuit *c, void *stream, double *d_rho);
+
 /* Copies the final string set of the last evaluation to host arrays in
  * canonical order (by z, then x), synchronizing `stream`.  DENSE with
  * PP_OPT_TRACK_TERMS = 1 for that evaluation returns the structural set (exact

@@ -161,6 +161,17 @@ class Circuit:
                                       ctypes.c_void_p(ev.data_ptr()), ctypes.c_void_p(grad.data_ptr())))
         return ev, grad[: self.n_params]
 
+    def density_matrix(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """rho = U|0><0|U^dag as a complex128 (2^n, 2^n) CUDA tensor (n <= 12);
+        basis bit q is qubit q.  `out`, if given, is a float64 CUDA tensor of
+        shape (2^n, 2^n, 2) that receives (real, imaginary) pairs."""
+        N = 1 << self.n
+        if out is None:
+            out = torch.empty((N, N, 2), dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous() and out.numel() == 2 * N * N
+        L.check(self._lib.pp_density_matrix(self._h, _stream(stream), ctypes.c_void_p(out.data_ptr())))
+        return torch.view_as_complex(out.view(N, N, 2))
+
     def terms(self, capacity=None, stream=None):
         """Final string set of the last evaluation, canonical order (z, then x)."""
         if capacity is None:

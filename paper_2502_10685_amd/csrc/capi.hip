@@ -71,6 +71,7 @@ __global__ void compact_to_sparse_count_kernel(const unsigned long long *total, 
 
 constexpr int kResidentMaxN = 7;
 constexpr int kDenseMaxN = 16;
+constexpr int kDensityMaxN = 12;
 // 32-bit tile offsets in the sparse kernels: 2x the capacity stays below 2^31
 constexpr int64_t kSparseMaxTerms = (int64_t)1 << 29;
 constexpr int kAutoDenseMaxN = 13;
@@ -178,6 +179,13 @@ struct pp_circuit {
 
     int track = 0, tile_opt = 0, use_graph = 0, block = 0;
     int64_t max_terms = 0;
+    int keep_coef = 0;  // LDS-resident runs store their final weights (density matrix)
+    int fwd_maps = 0;   // maps are forward maps g P g^dag (the gate list is then read backwards)
+    uint64_t gates_gen = 0;  // bumped by every pp_circuit_load_gates
+
+    // density matrix: Heisenberg propagation of the inverse circuit
+    pp_circuit *dm = nullptr;
+    uint64_t dm_gen = ~0ull;
 
     // schedule cache
     bool plan_valid = false;
@@ -430,13 +438,13 @@ pp_status ensure_plan(pp_circuit *c) {
         if ((r = upload_vec(&c->d_rop, P.rop)) != PP_OK) return r;
         if ((r = upload_vec(&c->d_rparam, P.rparam)) != PP_OK) return r;
         HIPCHK(dalloc(&c->d_maps, (size_t)9 * std::max(P.nmaps(), 1)));
-        c->h_comp = pp::ComposeDesc{c->d_roff, c->d_rop, c->d_rparam, c->d_theta, c->d_maps, P.nmaps(), 0};
+        c->h_comp = pp::ComposeDesc{c->d_roff, c->d_rop, c->d_rparam, c->d_theta, c->d_maps, P.nmaps(), c->fwd_maps};
         HIPCHK(dalloc(&c->d_comp, 1));
         HIPCHK(hipMemcpy(c->d_comp, &c->h_comp, sizeof(c->h_comp), hipMemcpyHostToDevice));
         if (P.resident) {
             pp::ResidentDesc &d = c->h_res;
             d = pp::ResidentDesc{};
-            d.coef_out = c->track ? c->coef : nullptr;
+            d.coef_out = (c->track || c->keep_coef) ? c->coef : nullptr;
             d.pres_out = c->track ? c->pres : nullptr;
             d.ops = c->d_ops;
             d.maps = c->d_maps;
@@ -628,6 +636,7 @@ void pp_circuit_destroy(pp_circuit *c) {
     if (!c) return;
     if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
     (void)hipDeviceSynchronize();
+    if (c->dm) pp_circuit_destroy(c->dm);
     free_plan_buffers(c);
     free_state_buffers(c);
     dfree(c->d_theta);
@@ -720,6 +729,7 @@ pp_status pp_circuit_load_gates(pp_circuit *c, int64_t m, const uint8_t *op, con
     c->g.n_params = n_params;
     if (n_params == 0) c->have_theta = true;
     c->have_gates = true;
+    c->gates_gen++;
     free_plan_buffers(c);
     c->evaluated = false;
     return PP_OK;
@@ -967,6 +977,65 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
     dfree(tmp.hist);
     dfree(tmp.tile_flags);
     return r;
+}
+
+// Density matrix (the paper's toDM task).  rho = U |0><0| U^dag = 2^-n sum over
+// the stabilizer group of U Z^z U^dag (eq. (3)): the 2^n strings Z^z with
+// weight 1 are propagated in the Schrodinger picture, P -> g P g^dag, g_1
+// first.  An internal circuit holds the gates in reverse order, so the dense
+// engine (which processes its last gate first) meets g_1 first, and its maps
+// are composed as forward maps (each gate's Heisenberg matrix transposed; CX
+// is its own inverse).
+pp_status pp_density_matrix(pp_circuit *c, void *stream, double *d_rho) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    if (!d_rho) return fail(PP_ERR_INVALID, "d_rho is NULL");
+    if (c->n > kDensityMaxN) return fail(PP_ERR_INVALID, "density matrix needs n <= 12");
+    if (!c->have_gates || !c->have_theta) return fail(PP_ERR_STATE, "load gates and theta first");
+    hipStream_t s = (hipStream_t)stream;
+    pp_status r = PP_OK;
+    if (!c->dm || c->dm_gen != c->gates_gen) {
+        if (c->dm) {
+            pp_circuit_destroy(c->dm);
+            c->dm = nullptr;
+        }
+        const int64_t m = c->g.m;
+        std::vector<uint8_t> op((size_t)m);
+        std::vector<int32_t> q0((size_t)m), q1((size_t)m), pa((size_t)m);
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t j = m - 1 - i;
+            op[(size_t)i] = c->g.op[(size_t)j];
+            q0[(size_t)i] = c->g.q0[(size_t)j];
+            q1[(size_t)i] = c->g.q1[(size_t)j];
+            pa[(size_t)i] = c->g.param[(size_t)j];
+        }
+        pp_circuit *a = nullptr;
+        if ((r = pp_circuit_create(c->n, c->dtype, PP_ENGINE_DENSE, &a)) != PP_OK) return r;
+        r = pp_circuit_load_gates(a, (int64_t)op.size(), op.data(), q0.data(), q1.data(), pa.data(), c->g.n_params);
+        if (r == PP_OK) {
+            const int64_t N = (int64_t)1 << c->n;
+            std::vector<uint64_t> xs((size_t)N, 0), zs((size_t)N);
+            std::vector<double> cs((size_t)N, 1.0);
+            for (int64_t j = 0; j < N; ++j) zs[(size_t)j] = (uint64_t)j;
+            r = pp_circuit_set_observable(a, N, xs.data(), zs.data(), cs.data());
+        }
+        if (r != PP_OK) {
+            pp_circuit_destroy(a);
+            return r;
+        }
+        a->keep_coef = 1;
+        a->fwd_maps = 1;
+        c->dm = a;
+        c->dm_gen = c->gates_gen;
+    }
+    pp_circuit *a = c->dm;
+    if (a->tile_opt != c->tile_opt && (r = pp_circuit_set_option(a, PP_OPT_TILE_QUBITS, c->tile_opt)) != PP_OK)
+        return r;
+    if ((r = pp_circuit_set_theta(a, c->d_theta, 1, stream)) != PP_OK) return r;
+    if ((r = ensure_state(a)) != PP_OK) return r;
+    if ((r = pp_evaluate(a, stream, a->d_result)) != PP_OK) return r;
+    HIPCHK(pp::launch_density_decode(a->coef, a->n, a->dbytes, d_rho, s));
+    c->last_stream = s;
+    return PP_OK;
 }
 
 }  // extern "C"

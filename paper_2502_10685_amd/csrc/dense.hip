@@ -1319,6 +1319,83 @@ __global__ void copy_f64_n_kernel(const double *src, double *dst, long long coun
         dst[i] = src[i];
 }
 
+// ------------------------------------------------------- density matrix
+// rho = 2^-n sum_Q r_Q Q from the Pauli weights r of 2^n rho (slot order; the
+// sum form of the density operator over the stabilizer group, eq. (3)).  A
+// string Q = (x, z) with Y = iXZ has one nonzero per column (Sec. III-D):
+// <a|Q|b> = [a = b ^ x] i^|x & z| (-1)^|b & z|.  So for a fixed x the column
+// entries rho[b ^ x][b] over all b are the Walsh-Hadamard transform over z of
+// r(x, z) i^|x & z|.  Workgroup x gathers those 2^n weights into LDS (real
+// and imaginary parts), runs the n butterfly stages and writes its 2^n
+// entries.  rho is row-major complex (re, im) doubles, rho[a][b] at
+// 2 (a 2^n + b); basis bit q is qubit q.
+__device__ __forceinline__ unsigned long long spread_bits(unsigned v) {
+    unsigned long long r = 0;
+    for (int q = 0; v; ++q, v >>= 1) r |= (unsigned long long)(v & 1u) << (2 * q);
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void density_decode_kernel(const T *__restrict__ coef, int n,
+                                                             double *__restrict__ rho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = 1 << n;
+    double *re = reinterpret_cast<double *>(smem);
+    double *im = re + N;
+    const unsigned x = blockIdx.x;
+    const unsigned long long sx = spread_bits(x);
+    for (int z = threadIdx.x; z < N; z += blockDim.x) {
+        const double w = (double)coef[sx | (spread_bits((unsigned)z) << 1)];
+        const int k = __popc(x & (unsigned)z) & 3;  // the phase i^k
+        re[z] = k == 0 ? w : (k == 2 ? -w : 0.0);
+        im[z] = k == 1 ? w : (k == 3 ? -w : 0.0);
+    }
+    __syncthreads();
+    for (int h = 1; h < N; h <<= 1) {
+        for (int t = threadIdx.x; t < N / 2; t += blockDim.x) {
+            const int i = ((t & ~(h - 1)) << 1) | (t & (h - 1)), j = i | h;
+            const double a = re[i], b = re[j], c = im[i], d = im[j];
+            re[i] = a + b;
+            re[j] = a - b;
+            im[i] = c + d;
+            im[j] = c - d;
+        }
+        __syncthreads();
+    }
+    const double scale = 1.0 / (double)N;
+    for (int b = threadIdx.x; b < N; b += blockDim.x) {
+        const size_t e = 2 * ((size_t)((unsigned)b ^ x) * (size_t)N + (size_t)b);
+        rho[e] = re[b] * scale;
+        rho[e + 1] = im[b] * scale;
+    }
+}
+
+hipError_t launch_density_decode(const void *coef, int n, int dtype_bytes, double *rho, hipStream_t s) {
+    if (n < 1 || n > 12) return hipErrorInvalidValue;
+    const size_t lds = (size_t)2 * ((size_t)1 << n) * sizeof(double);
+    const dim3 grid(1u << n), block(n >= 8 ? 256 : 64);
+    if (dtype_bytes == 8) {
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void *)density_decode_kernel<double>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        hipLaunchKernelGGL(density_decode_kernel<double>, grid, block, lds, s, (const double *)coef, n, rho);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void *)density_decode_kernel<float>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        hipLaunchKernelGGL(density_decode_kernel<float>, grid, block, lds, s, (const float *)coef, n, rho);
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------- map composer
 // maps[i] = G_last * ... * G_first over the recipe of op i, where G is the
 // Heisenberg matrix of one gate acting on the (X, Y, Z) weights:
@@ -1355,8 +1432,21 @@ __device__ __forceinline__ void mat3_mul(const double A[9], const double B[9], d
         for (int b = 0; b < 3; ++b) C[3 * a + b] = A[3 * a] * B[b] + A[3 * a + 1] * B[3 + b] + A[3 * a + 2] * B[6 + b];
 }
 
+// A descriptor with reserved = 1 composes forward maps (P -> g P g^dag): the
+// transpose of each gate's Heisenberg matrix, since the maps are orthogonal.
+__device__ __forceinline__ void gate_matrix_dir(int op, double th, bool fwd, double G[9]) {
+    gate_matrix(op, th, G);
+    if (fwd) {
+        double t;
+        t = G[1]; G[1] = G[3]; G[3] = t;
+        t = G[2]; G[2] = G[6]; G[6] = t;
+        t = G[5]; G[5] = G[7]; G[7] = t;
+    }
+}
+
 __global__ __launch_bounds__(256) void compose_kernel(const ComposeDesc *__restrict__ descs) {
     const ComposeDesc &d = descs[blockIdx.x];
+    const bool fwd = d.reserved == 1;
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int wstride = gridDim.y * wpb;
@@ -1371,7 +1461,7 @@ __global__ __launch_bounds__(256) void compose_kernel(const ComposeDesc *__restr
                 for (int r = r0; r < r1; ++r) {
                     const int op = d.rop[r];
                     double G[9], P[9];
-                    gate_matrix(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, G);
+                    gate_matrix_dir(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, fwd, G);
                     mat3_mul(G, M, P);
                     for (int t = 0; t < 9; ++t) M[t] = P[t];
                 }
@@ -1390,7 +1480,7 @@ __global__ __launch_bounds__(256) void compose_kernel(const ComposeDesc *__restr
                 const int r = c0 + lane;
                 if (r < r1) {
                     const int op = d.rop[r];
-                    gate_matrix(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, G);
+                    gate_matrix_dir(op, op >= 3 ? d.theta[d.rparam[r]] : 0.0, fwd, G);
                 }
                 // lane l holds the product of gates [c0 + l, c0 + l + w) after
                 // the step of width w; combine with the next block on the left

@@ -117,7 +117,7 @@ struct ComposeDesc {
     const double *theta;
     double *maps;
     int32_t nmaps;
-    int32_t reserved;
+    int32_t reserved;  // 1: forward maps (each gate's Heisenberg matrix transposed)
 };
 
 // --------------------------------------------------------------- sparse ops
@@ -160,6 +160,9 @@ hipError_t launch_dense_readout(const void *coef, int n, int dtype_bytes, double
 // the same for the nd circuits of a batch (one fill, one scatter launch;
 // one readout launch), each circuit with the single-circuit arithmetic
 hipError_t launch_dense_init_many(const DenseIODesc *d_descs, int nd, int max_n, int dtype_bytes, hipStream_t s);
+// rho (2^n x 2^n complex, row-major (re, im) doubles) from the 4^n Pauli
+// weights of 2^n rho in slot order; n <= 12
+hipError_t launch_density_decode(const void *coef, int n, int dtype_bytes, double *rho, hipStream_t s);
 hipError_t launch_dense_readout_many(const DenseIODesc *d_descs, int nd, int dtype_bytes, hipStream_t s);
 hipError_t launch_dense_count(const uint8_t *pres, int n, unsigned long long *out, hipStream_t s);
 hipError_t launch_dense_compact(const void *coef, const uint8_t *pres, int n, int dtype_bytes, uint64_t *x,
