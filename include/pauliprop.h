@@ -202,6 +202,23 @@ PP_API pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_eve
  * without gates or theta.  Enqueued on `stream`. */
 PP_API pp_status pp_density_matrix(pp_circuit *c, void *stream, double *d_rho);
 
+/* Truncated propagation (approximate; not part of the paper's exact method,
+ * which keeps every string): SPARSE engine only (PP_ERR_STATE otherwise).
+ * From the next evaluation on, a split child with more than max_weight
+ * non-identity letters is not created, and after every merge a string with
+ * more letters or with |weight| < min_abs_coeff is dropped.  Each dropped
+ * string P of weight w changes <O> by at most |w| (|<psi|P|psi>| <= 1), so
+ * the summed absolute dropped weight (pp_get_truncation) bounds the error.
+ * min_abs_coeff = 0 and max_weight >= n (the defaults: 0, 64) is the exact
+ * method.  PP_ERR_INVALID for min_abs_coeff < 0 or max_weight outside
+ * [1, 64]. */
+PP_API pp_status pp_circuit_set_truncation(pp_circuit *c, double min_abs_coeff, int32_t max_weight);
+
+/* Summed absolute weight dropped by truncation during the last SPARSE
+ * evaluation (0 for an exact run); synchronizes `stream`.  PP_ERR_STATE
+ * before a SPARSE evaluation. */
+PP_API pp_status pp_get_truncation(pp_circuit *c, void *stream, double *dropped_abs);
+
 /* Copies the final string set of the last evaluation to host arrays in
  * canonical order (by z, then x), synchronizing `stream`.  DENSE with
  * PP_OPT_TRACK_TERMS = 1 for that evaluation returns the structural set (exact

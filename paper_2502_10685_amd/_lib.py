@@ -65,6 +65,8 @@ def load():
         "pp_evaluate_thetas": (st, [P, I64, P, I32, P, P]),
         "pp_gradient": (st, [P, P, I32, P, P]),
         "pp_density_matrix": (st, [P, P, P]),
+        "pp_circuit_set_truncation": (st, [P, ctypes.c_double, I32]),
+        "pp_get_truncation": (st, [P, P, P]),
         "pp_get_terms": (st, [P, P, I64, P, P, P, ctypes.POINTER(I64)]),
         "pp_get_stats": (st, [P, ctypes.POINTER(PPStats)]),
         "pp_server_create": (st, [I64, I32, ctypes.POINTER(P)]),

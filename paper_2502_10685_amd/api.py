@@ -172,6 +172,18 @@ class Circuit:
         L.check(self._lib.pp_density_matrix(self._h, _stream(stream), ctypes.c_void_p(out.data_ptr())))
         return torch.view_as_complex(out.view(N, N, 2))
 
+    def set_truncation(self, min_abs_coeff=0.0, max_weight=64):
+        """Approximate SPARSE propagation: drop strings heavier than max_weight
+        letters or lighter than min_abs_coeff (defaults: exact)."""
+        L.check(self._lib.pp_circuit_set_truncation(self._h, float(min_abs_coeff), int(max_weight)))
+
+    def truncation_dropped(self, stream=None) -> float:
+        """Summed |weight| dropped by truncation in the last evaluation; it
+        bounds the error of <O>."""
+        v = ctypes.c_double(0.0)
+        L.check(self._lib.pp_get_truncation(self._h, _stream(stream), ctypes.byref(v)))
+        return v.value
+
     def terms(self, capacity=None, stream=None):
         """Final string set of the last evaluation, canonical order (z, then x)."""
         if capacity is None:

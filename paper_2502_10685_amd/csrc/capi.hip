@@ -180,6 +180,10 @@ struct pp_circuit {
     int track = 0, tile_opt = 0, use_graph = 0, block = 0;
     int64_t max_terms = 0;
     int keep_coef = 0;  // LDS-resident runs store their final weights (density matrix)
+    // truncated propagation (SPARSE; off by default)
+    double trunc_eps = 0.0;
+    int trunc_w = 64;
+    double *d_dropped = nullptr;  // per-tile dropped weights + the evaluation's total
     int fwd_maps = 0;   // maps are forward maps g P g^dag (the gate list is then read backwards)
     uint64_t gates_gen = 0;  // bumped by every pp_circuit_load_gates
 
@@ -340,6 +344,7 @@ void free_state_buffers(pp_circuit *c) {
     dfree(c->sb.updates);
     dfree(c->sb.hist);
     dfree(c->sb.tile_flags);
+    dfree(c->d_dropped);
     c->sb = pp::SparseBuffers{};
 }
 
@@ -399,6 +404,7 @@ pp_status ensure_state(pp_circuit *c) {
         HIPCHK(dalloc(&c->sb.updates, 1));
         HIPCHK(dalloc(&c->sb.hist, (size_t)256 * tiles));
         HIPCHK(dalloc(&c->sb.tile_flags, (size_t)tiles));
+        HIPCHK(dalloc(&c->d_dropped, (size_t)tiles + 1));
         HIPCHK(dalloc(&c->d_partials, 256));
     }
     if (!c->d_counters) HIPCHK(dalloc(&c->d_counters, 4));
@@ -572,23 +578,29 @@ pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
 pp_status enqueue_sparse(pp_circuit *c, hipStream_t s, double *out) {
     const pp::SparsePlan &P = c->splan;
     if ((int64_t)c->ox.size() > c->sb.cap2) return fail(PP_ERR_CAPACITY, "observable larger than the term capacity");
-    HIPCHK(pp::launch_sparse_init(c->sb, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+    pp::SparseTrunc tr;
+    tr.on = (c->trunc_eps > 0.0 || c->trunc_w < c->n) ? 1 : 0;
+    tr.max_weight = c->trunc_w;
+    tr.eps = c->trunc_eps;
+    tr.dropped = c->d_dropped;
+    HIPCHK(pp::launch_sparse_init(c->sb, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s,
+                                  c->d_dropped + c->sb.max_tiles));
     bool merged_last = true;
     for (const pp::SparsePassDesc &p : P.passes) {
         {
             ProfScope ps(PC_SPASS, s);
-            HIPCHK(pp::launch_sparse_pass(c->sb, c->dbytes, c->d_codes, p, c->d_theta, s));
+            HIPCHK(pp::launch_sparse_pass(c->sb, c->dbytes, c->d_codes, p, c->d_theta, s, tr));
         }
         merged_last = false;
         if (p.rot_op >= 3) {
             ProfScope ps(PC_SMERGE, s);
-            HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s));
+            HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s, tr));
             merged_last = true;
         }
     }
     if (!merged_last) {
         ProfScope ps(PC_SMERGE, s);
-        HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s));
+        HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s, tr));
     }
     {
         ProfScope ps(PC_READOUT, s);
@@ -1035,6 +1047,25 @@ pp_status pp_density_matrix(pp_circuit *c, void *stream, double *d_rho) {
     if ((r = pp_evaluate(a, stream, a->d_result)) != PP_OK) return r;
     HIPCHK(pp::launch_density_decode(a->coef, a->n, a->dbytes, d_rho, s));
     c->last_stream = s;
+    return PP_OK;
+}
+
+pp_status pp_circuit_set_truncation(pp_circuit *c, double min_abs_coeff, int32_t max_weight) {
+    if (!c) return fail(PP_ERR_INVALID, "null circuit");
+    if (c->engine != PP_ENGINE_SPARSE) return fail(PP_ERR_STATE, "truncation needs the SPARSE engine");
+    if (!(min_abs_coeff >= 0.0) || min_abs_coeff > 1e300) return fail(PP_ERR_INVALID, "min_abs_coeff must be >= 0");
+    if (max_weight < 1 || max_weight > 64) return fail(PP_ERR_INVALID, "max_weight must be in [1, 64]");
+    c->trunc_eps = min_abs_coeff;
+    c->trunc_w = max_weight;
+    return PP_OK;
+}
+
+pp_status pp_get_truncation(pp_circuit *c, void *stream, double *dropped_abs) {
+    if (!c || !dropped_abs) return fail(PP_ERR_INVALID, "null argument");
+    if (c->engine != PP_ENGINE_SPARSE || !c->d_dropped || !c->evaluated)
+        return fail(PP_ERR_STATE, "no SPARSE evaluation yet");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(hipMemcpy(dropped_abs, c->d_dropped + c->sb.max_tiles, sizeof(double), hipMemcpyDeviceToHost));
     return PP_OK;
 }
 

@@ -190,10 +190,23 @@ struct SparseBuffers {
     int64_t max_tiles;
 };
 hipError_t launch_sparse_init(SparseBuffers &b, int dtype_bytes, const uint64_t *x, const uint64_t *z,
-                              const double *c, int nterms, hipStream_t s);
+                              const double *c, int nterms, hipStream_t s, double *dropped_total = nullptr);
+// Truncated propagation (approximate; off when on == 0): a split child with
+// more than max_weight non-identity letters is not written, and a merged
+// string with more letters or with |weight| < eps is dropped.  The absolute
+// weight dropped is summed per tile into dropped[0, tiles) and added, in a
+// fixed order, to dropped[max_tiles] (reset by launch_sparse_init).
+struct SparseTrunc {
+    int32_t on = 0;
+    int32_t max_weight = 64;
+    double eps = 0.0;
+    double *dropped = nullptr;  // max_tiles + 1 doubles
+};
 hipError_t launch_sparse_pass(SparseBuffers &b, int dtype_bytes, const uint32_t *cliff_codes,
-                              const SparsePassDesc &p, const double *theta, hipStream_t s);
-hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStream_t s);
+                              const SparsePassDesc &p, const double *theta, hipStream_t s,
+                              const SparseTrunc &tr = SparseTrunc{});
+hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStream_t s,
+                               const SparseTrunc &tr = SparseTrunc{});
 hipError_t launch_sparse_readout(SparseBuffers &b, int dtype_bytes, double *partials, double *out,
                                  hipStream_t s);
 

@@ -57,6 +57,20 @@ __device__ __forceinline__ void clifford_apply(uint64_t &x, uint64_t &z, unsigne
     }
 }
 
+// non-identity letters of a string
+__device__ __forceinline__ int pauli_weight(uint64_t x, uint64_t z) { return __popcll(x | z); }
+
+// sum over a SP_BLOCK workgroup in a fixed order (lanes, then waves)
+__device__ __forceinline__ double block_sum_d(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < SP_BLOCK / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
 // anticommutation with sigma on qubit q, the child's flipped bits and sign
 __device__ __forceinline__ bool rot_child(int op, int q, uint64_t x, uint64_t z, uint64_t &fx, uint64_t &fz, double &sg) {
     const unsigned xb = (unsigned)(x >> q) & 1u, zb = (unsigned)(z >> q) & 1u;
@@ -83,7 +97,7 @@ __device__ __forceinline__ long long live_tiles(long long T) { return (T + SP_TI
 __global__ __launch_bounds__(SP_BLOCK) void pass_count_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z,
                                                              const long long *__restrict__ count,
                                                              const uint32_t *__restrict__ codes, SparsePassDesc p,
-                                                             int *__restrict__ bcounts) {
+                                                             int *__restrict__ bcounts, int max_weight) {
     __shared__ int red[SP_BLOCK / 64];
     const long long T = count[0];
     const long long L = live_tiles(T);
@@ -99,7 +113,10 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_count_kernel(const uint64_t *__
                     clifford_apply(xx, zz, neg, codes, p.g_begin, p.g_end);
                     uint64_t fx, fz;
                     double sg;
-                    mine += rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg) ? 1 : 0;
+                    mine += (rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg) &&
+                             pauli_weight(xx ^ fx, zz ^ fz) <= max_weight)
+                                ? 1
+                                : 0;
                 }
             }
         }
@@ -207,9 +224,11 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_write_kernel(uint64_t *__restri
                                                              const long long *__restrict__ child_base, long long cap2,
                                                              const uint32_t *__restrict__ codes, SparsePassDesc p,
                                                              const double *__restrict__ theta,
-                                                             const int *__restrict__ boffs) {
+                                                             const int *__restrict__ boffs, int max_weight,
+                                                             double *__restrict__ dropped) {
     __shared__ int wcnt[SP_BLOCK / 64];
     __shared__ int running;
+    __shared__ double redd[SP_BLOCK / 64];
     const long long nlive = child_base[0];
     const long long L = live_tiles(nlive);
     if ((long long)blockIdx.x >= L) return;
@@ -221,12 +240,13 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_write_kernel(uint64_t *__restri
         const long long b0 = t * SP_TILE;
         if (threadIdx.x == 0) running = boffs[t];
         __syncthreads();
+        double lost = 0.0;  // weight of children above max_weight (truncation)
         for (int it = 0; it < SP_ITEMS; ++it) {
             const long long i = b0 + it * SP_BLOCK + threadIdx.x;
             const bool live = i < nlive;
             uint64_t xx = 0, zz = 0, fx = 0, fz = 0;
             double cc = 0.0, sg = 1.0;
-            bool anti = false;
+            bool anti = false, split = false;
             if (live) {
                 xx = x[i];
                 zz = z[i];
@@ -234,7 +254,9 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_write_kernel(uint64_t *__restri
                 unsigned neg = 0;
                 clifford_apply(xx, zz, neg, codes, p.g_begin, p.g_end);
                 if (neg) cc = -cc;
-                if (rot) anti = rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg);
+                if (rot) split = rot_child(p.rot_op, p.rot_q, xx, zz, fx, fz, sg);
+                anti = split && pauli_weight(xx ^ fx, zz ^ fz) <= max_weight;
+                if (split && !anti) lost += fabs(cc * sg * sn);
             }
             const unsigned long long bal = __ballot(anti);
             const int below = __popcll(bal & ((1ull << lane) - 1ull));
@@ -245,7 +267,7 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_write_kernel(uint64_t *__restri
             if (live) {
                 x[i] = xx;
                 z[i] = zz;
-                stc<T>(c, i, anti ? cc * cs : cc);
+                stc<T>(c, i, split ? cc * cs : cc);
                 if (anti) {
                     const long long j = nlive + off + below;
                     if (j < cap2) {
@@ -263,7 +285,23 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_write_kernel(uint64_t *__restri
             }
             __syncthreads();
         }
+        if (dropped) {
+            const double tl = block_sum_d(lost, redd);
+            if (threadIdx.x == 0) dropped[t] = tl;
+        }
     }
+}
+
+// Adds the per-tile dropped weights of the tiles of the kernel before
+// (live_tiles of *cnt) to dropped[total_at], in a fixed order.
+__global__ __launch_bounds__(SP_BLOCK) void trunc_total_kernel(double *__restrict__ dropped,
+                                                              const long long *__restrict__ cnt, long long total_at) {
+    __shared__ double redd[SP_BLOCK / 64];
+    const long long L = live_tiles(cnt[0]);
+    double v = 0.0;
+    for (long long t = threadIdx.x; t < L; t += SP_BLOCK) v += dropped[t];
+    v = block_sum_d(v, redd);
+    if (threadIdx.x == 0) dropped[total_at] += v;
 }
 
 // ---------------------------------------------------------- radix sort
@@ -402,8 +440,21 @@ __device__ __forceinline__ bool seg_head(const uint64_t *x, const uint64_t *z, l
     return i == 0 || x[i] != x[i - 1] || z[i] != z[i - 1];
 }
 
+// A merged string survives truncation if its weight and |sum| allow it
+template <typename T>
+__device__ __forceinline__ bool seg_keep(const uint64_t *x, const uint64_t *z, const void *c, long long i, long long nlive,
+                                         int max_weight, double eps, double &sum) {
+    double s = ldc<T>(c, i);
+    for (long long j = i + 1; j < nlive && x[j] == x[i] && z[j] == z[i]; ++j) s += ldc<T>(c, j);
+    sum = s;
+    return pauli_weight(x[i], z[i]) <= max_weight && fabs(s) >= eps;
+}
+
+template <typename TW>
 __global__ __launch_bounds__(SP_BLOCK) void seg_count_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z,
-                                                            const long long *__restrict__ count, int *__restrict__ bcounts) {
+                                                            const void *c, const long long *__restrict__ count,
+                                                            int *__restrict__ bcounts, int trunc, int max_weight,
+                                                            double eps) {
     __shared__ int red[SP_BLOCK / 64];
     const long long T = count[0];
     const long long L = live_tiles(T);
@@ -412,7 +463,10 @@ __global__ __launch_bounds__(SP_BLOCK) void seg_count_kernel(const uint64_t *__r
         int mine = 0;
         for (int it = 0; it < SP_ITEMS; ++it) {
             const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-            if (i < T && seg_head(x, z, i)) ++mine;
+            if (i < T && seg_head(x, z, i)) {
+                double s;
+                if (!trunc || seg_keep<TW>(x, z, c, i, T, max_weight, eps, s)) ++mine;
+            }
         }
         for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mine;
@@ -439,9 +493,11 @@ __global__ __launch_bounds__(SP_BLOCK) void seg_write_kernel(const uint64_t *__r
                                                             const void *c, uint64_t *__restrict__ xo,
                                                             uint64_t *__restrict__ zo, void *co,
                                                             const long long *__restrict__ old_count,
-                                                            const int *__restrict__ boffs) {
+                                                            const int *__restrict__ boffs, int trunc, int max_weight,
+                                                            double eps, double *__restrict__ dropped) {
     __shared__ int wcnt[SP_BLOCK / 64];
     __shared__ int running;
+    __shared__ double redd[SP_BLOCK / 64];
     const long long nlive = old_count[0];
     const long long L = live_tiles(nlive);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -449,9 +505,15 @@ __global__ __launch_bounds__(SP_BLOCK) void seg_write_kernel(const uint64_t *__r
         const long long b0 = t * SP_TILE;
         if (threadIdx.x == 0) running = boffs[t];
         __syncthreads();
+        double lost = 0.0;
         for (int it = 0; it < SP_ITEMS; ++it) {
             const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-            const bool head = i < nlive && seg_head(x, z, i);
+            bool head = i < nlive && seg_head(x, z, i);
+            double ts = 0.0;
+            if (head && trunc && !seg_keep<T>(x, z, c, i, nlive, max_weight, eps, ts)) {
+                lost += fabs(ts);
+                head = false;
+            }
             const unsigned long long bal = __ballot(head);
             const int below = __popcll(bal & ((1ull << lane) - 1ull));
             if (lane == 0) wcnt[w] = __popcll(bal);
@@ -473,6 +535,10 @@ __global__ __launch_bounds__(SP_BLOCK) void seg_write_kernel(const uint64_t *__r
                 running += s;
             }
             __syncthreads();
+        }
+        if (trunc) {
+            const double tl = block_sum_d(lost, redd);
+            if (threadIdx.x == 0) dropped[t] = tl;
         }
     }
 }
@@ -508,8 +574,10 @@ __global__ void sp_readout_final_kernel(const double *__restrict__ partials, con
 // ---------------------------------------------------------------- init
 template <typename T>
 __global__ void sp_init_kernel(uint64_t *x, uint64_t *z, void *c, long long *count, unsigned long long *updates,
-                               const uint64_t *ox, const uint64_t *oz, const double *oc, int nterms) {
+                               const uint64_t *ox, const uint64_t *oz, const double *oc, int nterms,
+                               double *dropped_total) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    if (dropped_total) *dropped_total = 0.0;
     for (int t = 0; t < nterms; ++t) {
         x[t] = ox[t];
         z[t] = oz[t];
@@ -534,35 +602,40 @@ static void launch_scan(V *a, const long long *count, int mult, SparseBuffers &b
 }
 
 hipError_t launch_sparse_init(SparseBuffers &b, int dtype_bytes, const uint64_t *x, const uint64_t *z,
-                              const double *c, int nterms, hipStream_t s) {
+                              const double *c, int nterms, hipStream_t s, double *dropped_total) {
     if (dtype_bytes == 8)
         hipLaunchKernelGGL(sp_init_kernel<double>, dim3(1), dim3(64), 0, s, b.x, b.z, b.c, b.count, b.updates, x, z,
-                           c, nterms);
+                           c, nterms, dropped_total);
     else
         hipLaunchKernelGGL(sp_init_kernel<float>, dim3(1), dim3(64), 0, s, b.x, b.z, b.c, b.count, b.updates, x, z, c,
-                           nterms);
+                           nterms, dropped_total);
     return hipGetLastError();
 }
 
 hipError_t launch_sparse_pass(SparseBuffers &b, int dtype_bytes, const uint32_t *codes, const SparsePassDesc &p,
-                              const double *theta, hipStream_t s) {
+                              const double *theta, hipStream_t s, const SparseTrunc &tr) {
     const int g = grid_for(b);
     int *bc = b.tile_flags;
     long long *child_base = b.count + 2, *total = b.count + 4;
-    hipLaunchKernelGGL(pass_count_kernel, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, codes, p, bc);
+    const int mw = tr.on ? tr.max_weight : 64;
+    double *drop = tr.on ? tr.dropped : nullptr;
+    hipLaunchKernelGGL(pass_count_kernel, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, codes, p, bc, mw);
     launch_scan<int>(bc, b.count, 1, b, total, s);
     hipLaunchKernelGGL(pass_finalize_kernel, dim3(1), dim3(64), 0, s, b.count, total, b.cap2, b.updates, p.ngates,
                        child_base);
     if (dtype_bytes == 8)
         hipLaunchKernelGGL(pass_write_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, child_base, b.cap2,
-                           codes, p, theta, bc);
+                           codes, p, theta, bc, mw, drop);
     else
         hipLaunchKernelGGL(pass_write_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, child_base, b.cap2,
-                           codes, p, theta, bc);
+                           codes, p, theta, bc, mw, drop);
+    if (drop)
+        hipLaunchKernelGGL(trunc_total_kernel, dim3(1), dim3(SP_BLOCK), 0, s, drop, child_base,
+                           (long long)b.max_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStream_t s) {
+hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStream_t s, const SparseTrunc &tr) {
     const int g = grid_for(b);
     const int key_bits = 2 * n;
     long long *old_count = b.count + 3, *total = b.count + 4;
@@ -580,15 +653,26 @@ hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStre
         std::swap(b.c, b.c2);
     }
     int *bc = b.tile_flags;
-    hipLaunchKernelGGL(seg_count_kernel, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, bc);
+    const int on = tr.on ? 1 : 0;
+    const int mw = tr.on ? tr.max_weight : 64;
+    const double eps = tr.on ? tr.eps : 0.0;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(seg_count_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.count, bc, on, mw,
+                           eps);
+    else
+        hipLaunchKernelGGL(seg_count_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.count, bc, on, mw,
+                           eps);
     launch_scan<int>(bc, b.count, 1, b, total, s);
     hipLaunchKernelGGL(seg_finalize_kernel, dim3(1), dim3(64), 0, s, b.count, total, old_count);
     if (dtype_bytes == 8)
         hipLaunchKernelGGL(seg_write_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2, b.c2,
-                           old_count, bc);
+                           old_count, bc, on, mw, eps, tr.dropped);
     else
         hipLaunchKernelGGL(seg_write_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2, b.c2,
-                           old_count, bc);
+                           old_count, bc, on, mw, eps, tr.dropped);
+    if (on)
+        hipLaunchKernelGGL(trunc_total_kernel, dim3(1), dim3(SP_BLOCK), 0, s, tr.dropped, old_count,
+                           (long long)b.max_tiles);
     std::swap(b.x, b.x2);
     std::swap(b.z, b.z2);
     std::swap(b.c, b.c2);
