@@ -259,6 +259,24 @@ def sparse_leg(api, torch):
                     "updates_per_s": st["term_updates"] / dt, "overflow": bool(st["overflow"]),
                     "expval": float(ev.item())})
         c.close()
+    # truncated propagation past the exact method's reach (approximate; the
+    # dropped weight bounds the error of <O>)
+    wc = W.random_circuit(np.random.default_rng(32), 32, 400, W.obs_z(32, [0, 1]))
+    c = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 24)
+    c.set_truncation(1e-7, 64)
+    c.evaluate()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ev = c.evaluate()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    st = c.stats()
+    out.append({"workload": "random n=32 m=400 seed 32, truncated (|c| >= 1e-7)", "gates": wc.m,
+                "ms": dt * 1e3, "final_terms": int(st["final_terms"]), "term_updates": int(st["term_updates"]),
+                "updates_per_s": st["term_updates"] / dt, "overflow": bool(st["overflow"]),
+                "expval": float(ev.item()), "dropped_weight_bound": c.truncation_dropped()})
+    c.close()
     return out
 
 
