@@ -328,8 +328,17 @@ def cpu_baseline(circs, gpu_vals, seconds, updates):
         names.append(i)
         if spent >= seconds:
             break
+    # context: the oracle's FP64 state vector on the same sample (the method
+    # works in the 4^n Pauli space; a state vector needs 2^n amplitudes)
+    t0 = time.perf_counter()
+    sv_err = 0.0
+    for i in names:
+        sv_err = max(sv_err, abs(oracle.expval_sv(circs[i]) - gpu_vals[i]))
+    sv_dt = time.perf_counter() - t0
     return {"value": done_u / spent if spent > 0 else None, "unit": "Pauli-term updates/s",
             "cores": 1, "kind": "oracle",
+            "statevector_circuits_per_s": len(names) / sv_dt if sv_dt > 0 else None,
+            "max_abs_err_gpu_vs_statevector": sv_err,
             "sample": (f"scalar Pauli propagator (C, merge after every gate, 1 thread) on {len(names)} "
                        f"of the workload's circuits (every 8th that fits a {seconds:.0f}s budget: "
                        f"{names[:10]}{'...' if len(names) > 10 else ''}), "
