@@ -86,10 +86,11 @@ typedef enum pp_option {
                                min(4^n, 2^24), at most 2^29); the buffers
                                hold 2x this */
     PP_OPT_USE_GRAPH = 3,   /* 1: replay a captured hipGraph for pp_evaluate
-                               (tiled DENSE) and for pp_gradient (the whole
-                               Heisenberg + adjoint sweep, a training step's
-                               launch sequence); theta is read from device
-                               memory at replay */
+                               (tiled DENSE, and SPARSE: its whole pass and
+                               merge sequence, which needs no host sync) and
+                               for pp_gradient (the whole Heisenberg + adjoint
+                               sweep, a training step's launch sequence);
+                               theta is read from device memory at replay */
     PP_OPT_BLOCK = 4        /* threads per workgroup (64..1024), 0 = default */
 } pp_option;
 

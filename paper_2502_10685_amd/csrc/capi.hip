@@ -834,16 +834,17 @@ pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval) {
     if ((r = ensure_plan(c)) != PP_OK) return r;
     hipStream_t s = (hipStream_t)stream;
     fill_plan_stats(c);
-    if (c->engine == PP_ENGINE_SPARSE) {
-        r = enqueue_sparse(c, s, d_expval);
-    } else if (c->use_graph && !c->dplan.resident) {
+    const bool sparse = c->engine == PP_ENGINE_SPARSE;
+    if (c->use_graph && (sparse || !c->dplan.resident)) {
+        // the whole evaluation is device-driven (no host synchronization),
+        // so it is captured once and replayed; theta is read at replay
         if (!c->gexec) {
             hipStream_t cs;
             HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
                 g_prof.capturing++;
-                r = enqueue_dense_body(c, cs, c->d_result);
+                r = sparse ? enqueue_sparse(c, cs, c->d_result) : enqueue_dense_body(c, cs, c->d_result);
                 g_prof.capturing--;
                 hipGraph_t gr = nullptr;
                 hipError_t e2 = hipStreamEndCapture(cs, &gr);
@@ -864,6 +865,8 @@ pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval) {
         HIPCHK(hipGraphLaunch(c->gexec, s));
         hipLaunchKernelGGL(copy_f64_kernel, dim3(1), dim3(64), 0, s, c->d_result, d_expval, 1);
         HIPCHK(hipGetLastError());
+    } else if (sparse) {
+        r = enqueue_sparse(c, s, d_expval);
     } else {
         r = enqueue_dense_body(c, s, d_expval);
     }
@@ -1057,6 +1060,7 @@ pp_status pp_circuit_set_truncation(pp_circuit *c, double min_abs_coeff, int32_t
     if (max_weight < 1 || max_weight > 64) return fail(PP_ERR_INVALID, "max_weight must be in [1, 64]");
     c->trunc_eps = min_abs_coeff;
     c->trunc_w = max_weight;
+    free_graph(c);  // a captured evaluation holds the old cuts
     return PP_OK;
 }
 

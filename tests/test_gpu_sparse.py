@@ -96,3 +96,33 @@ def test_sparse_beyond_grid_stride_statevector(api):
     assert abs(float(np.sum(v * v)) - 1.0) <= 1e-10
     assert abs(float(np.sum(v[x == 0])) - ev) <= TOL64
     c.close()
+
+
+def test_sparse_graph_replay_matches_eager(api):
+    """The sparse evaluation captured once as a hipGraph and replayed: every
+    replay (with eager work of another circuit in between, and with new theta)
+    equals the eager evaluation bit for bit, strings and weights included."""
+    import torch
+    wc = W.random_circuit(np.random.default_rng(21), 12, 220, W.obs_z(12, [0, 1]))
+    _say("sparse graph replay n=12")
+    eager = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 22)
+    graph = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 22, use_graph=True)
+    other = api.Circuit.from_workload(W.random_circuit(np.random.default_rng(5), 8, 100), engine="sparse")
+    rng = np.random.default_rng(99)
+    for rep in range(4):
+        th = wc.theta if rep == 0 else rng.uniform(0, 2 * np.pi, wc.n_params)
+        eager.set_theta(th)
+        graph.set_theta(th)
+        e1 = float(eager.evaluate().item())
+        other.evaluate()
+        e2 = float(graph.evaluate().item())
+        torch.cuda.synchronize()
+        assert e1 == e2, (rep, e1, e2)
+        x1, z1, c1 = eager.terms(capacity=1 << 22)
+        x2, z2, c2 = graph.terms(capacity=1 << 22)
+        assert np.array_equal(x1, x2) and np.array_equal(z1, z2)
+        assert np.array_equal(c1.view(np.uint64), c2.view(np.uint64))
+        assert eager.stats()["term_updates"] == graph.stats()["term_updates"]
+    assert abs(e1 - oracle.expval_sv(wc.with_theta(th))) <= TOL64
+    for c in (eager, graph, other):
+        c.close()
