@@ -45,6 +45,11 @@ def test_version_and_null_safety_without_gpu():
     assert lib.pp_circuit_create(65, 0, 0, ctypes.byref(h)) == L.PP_ERR_INVALID
     assert lib.pp_circuit_create(4, 7, 0, ctypes.byref(h)) == L.PP_ERR_INVALID
     assert b"dtype" in lib.pp_last_error()
+    # entry points of the density matrix and of truncation reject NULL first
+    assert lib.pp_density_matrix(None, None, None) == L.PP_ERR_INVALID
+    assert lib.pp_circuit_set_truncation(None, 0.0, 4) == L.PP_ERR_INVALID
+    v = ctypes.c_double(0.0)
+    assert lib.pp_get_truncation(None, None, ctypes.byref(v)) == L.PP_ERR_INVALID
 
 
 def test_stats_struct_layout_matches_header():
