@@ -186,6 +186,25 @@ def test_config3_sampled_circuits(api, idx):
     assert abs(ev - sv) <= TOL64, (ev, sv)
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_config3_full_batch_every_output(api, dtype, tol):
+    """The 512-circuit batch in the launch configuration the benchmark times
+    (one pp_evaluate_batch, default kernels): every output against the
+    oracle's state vector."""
+    import torch
+    circs = _config3()
+    _say(f"config3 full batch {dtype}")
+    objs = [api.Circuit.from_workload(w, dtype=dtype) for w in circs]
+    out = api.evaluate_batch(objs)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = np.array([oracle.expval_sv(w) for w in circs])
+    err = np.abs(got - want)
+    assert float(err.max()) <= tol, (int(err.argmax()), float(err.max()))
+    for o in objs:
+        o.close()
+
+
 def test_n12_sampled(api):
     rng = np.random.default_rng(12)
     wc = W.random_circuit(rng, 12, 1500, W.obs_z(12, [0]))
