@@ -316,9 +316,14 @@ PP_API pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *
                                     int32_t compose, int32_t reorder, int64_t *n_ops, int64_t *n_passes,
                                     int32_t *pass_ops, int64_t max_passes);
 
-/* Kernel timing for measurement: while enabled (on = 1), every kernel launch
- * of the library is bracketed by a pair of HIP events recorded on the stream
- * it is launched on.  on = 0 stops recording.  Not thread-safe; meant for
+/* Kernel timing for measurement: while enabled (on = 1), the library's
+ * kernel launches are timed with HIP events recorded on the stream they are
+ * launched on.  A run of consecutive tile passes (one call's passes on one
+ * stream) is bracketed by one pair of events and each of its launches is
+ * credited with the run's mean duration, so the passes still run back to
+ * back; every other launch is bracketed by its own pair (each recorded event
+ * delays the next kernel by a few microseconds).  The events carry no
+ * system-scope fence.  on = 0 stops recording.  Not thread-safe; meant for
  * benchmarks. */
 PP_API pp_status pp_profile_enable(int32_t on);
 

@@ -126,11 +126,13 @@ struct Prof {
     int capturing = 0;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    std::vector<std::pair<int, size_t>> recs;  // class, index of the start event
+    struct Rec { int cls; size_t start; int64_t launches; };
+    std::vector<Rec> recs;  // class, index of the start event (stop: next), launches timed
     hipEvent_t take() {
         if (used == pool.size()) {
             hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            // timing only: no system-scope fence (no L2 write-back at each event)
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             pool.push_back(e);
         }
         return pool[used++];
@@ -138,7 +140,10 @@ struct Prof {
 };
 Prof g_prof;
 
-// Brackets the launches made during its lifetime with two events.
+// Brackets the launches made during its lifetime with two recorded events.
+// Each recorded event is a marker packet that delays the next kernel by a
+// few microseconds, so runs of back-to-back tile passes are timed as a whole
+// by TileSpan instead.
 struct ProfScope {
     int cls;
     hipStream_t s;
@@ -153,8 +158,37 @@ struct ProfScope {
     }
     ~ProfScope() {
         if (!active) return;
-        if (hipEventRecord(g_prof.pool[idx + 1], s) == hipSuccess) g_prof.recs.push_back({cls, idx});
+        if (hipEventRecord(g_prof.pool[idx + 1], s) == hipSuccess) g_prof.recs.push_back({cls, idx, 1});
     }
+};
+
+// Times a run of consecutive tile-pass launches on one stream with one pair
+// of events around the whole run (nothing else is launched on that stream in
+// between); each launch is credited with the run's mean duration.  The passes
+// then run back to back, and the mean equals the kernels' mean duration.
+struct TileSpan {
+    hipStream_t s = nullptr;
+    size_t idx = 0;
+    int64_t launches = 0;
+    bool open = false;
+    void begin(hipStream_t st) {
+        if (open || !g_prof.on || g_prof.capturing) return;
+        s = st;
+        idx = g_prof.used;
+        hipEvent_t a = g_prof.take(), b = g_prof.take();
+        open = a && b && hipEventRecord(a, s) == hipSuccess;
+        launches = 0;
+    }
+    void count() {
+        if (open) ++launches;
+    }
+    void end() {
+        if (!open) return;
+        open = false;
+        if (launches > 0 && hipEventRecord(g_prof.pool[idx + 1], s) == hipSuccess)
+            g_prof.recs.push_back({PC_TILE, idx, launches});
+    }
+    ~TileSpan() { end(); }
 };
 
 }  // namespace
@@ -557,6 +591,8 @@ pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
                                      c->d_oc, (int)c->ox.size(), s));
     }
     const int shift = 2 * (c->n - P.k);
+    TileSpan span;
+    span.begin(s);
     for (size_t p = 0; p < P.passes.size(); ++p) {
         pp::TileGroups grp{};
         grp.ngroups = 1;
@@ -564,9 +600,10 @@ pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
         grp.first_block[1] = 1 << shift;
         grp.first_desc[0] = (int32_t)p;
         grp.shift[0] = shift;
-        ProfScope ps(PC_TILE, s);
         HIPCHK(pp::launch_tile_pass(c->d_pass, grp, P.k, c->dbytes, c->track != 0, s));
+        span.count();
     }
+    span.end();
     {
         ProfScope ps(PC_READOUT, s);
         HIPCHK(pp::launch_dense_readout(c->coef, c->n, c->dbytes, out, s));
@@ -1244,22 +1281,28 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         HIPCHK(hipEventCreateWithFlags(&B.join, hipEventDisableTiming));
     }
     bool forked = false;
+    TileSpan span;  // the tile passes come last in the list, all on s
     for (const auto &L : B.launches) {
         if (L.kind == 1 && !forked) {  // after the maps are composed
             HIPCHK(hipEventRecord(B.fork, s));
             HIPCHK(hipStreamWaitEvent(B.aux, B.fork, 0));
             forked = true;
         }
-        hipStream_t ls = L.kind == 1 ? B.aux : s;
-        ProfScope ps(L.kind == 0 ? PC_COMPOSE : L.kind == 1 ? PC_RES : PC_TILE, ls);
-        if (L.kind == 0) {
-            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, ls, L.nblocks));
-        } else if (L.kind == 1) {
-            HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, ls));
-        } else {
-            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.tg, L.group_n, dbytes, false, ls));
+        if (L.kind == 2) {
+            span.begin(s);
+            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.tg, L.group_n, dbytes, false, s));
+            span.count();
+            continue;
         }
+        span.end();
+        hipStream_t ls = L.kind == 1 ? B.aux : s;
+        ProfScope ps(L.kind == 0 ? PC_COMPOSE : PC_RES, ls);
+        if (L.kind == 0)
+            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, ls, L.nblocks));
+        else
+            HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, ls));
     }
+    span.end();
     if (forked) {
         HIPCHK(hipEventRecord(B.join, B.aux));
         HIPCHK(hipStreamWaitEvent(s, B.join, 0));
@@ -1502,6 +1545,8 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
     const int shift = 2 * (c->n - P.k);
     const int64_t ntiles = (int64_t)1 << shift;
     if (count * ntiles > INT32_MAX) return fail(PP_ERR_INVALID, "too many tiles in one sweep launch");
+    TileSpan span;
+    span.begin(s);
     for (size_t l = 0; l < P.passes.size(); ++l) {
         // one launch: the sets' descriptors of pass l are consecutive
         pp::TileGroups grp{};
@@ -1510,10 +1555,11 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
         grp.first_block[1] = (int32_t)(count * ntiles);
         grp.first_desc[0] = 0;
         grp.shift[0] = shift;
-        ProfScope ps(PC_TILE, s);
         HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + W.pass_off) + l * count, grp, P.k, c->dbytes,
                                     false, s));
+        span.count();
     }
+    span.end();
     {
         ProfScope ps(PC_READOUT, s);
         HIPCHK(pp::launch_dense_readout(W.coef, c->n, c->dbytes, d_expvals, s, (int)count));
@@ -1602,15 +1648,18 @@ pp_status enqueue_gradient_body(pp_circuit *c, hipStream_t s, double *d_expval, 
                 HIPCHK(pp::launch_dense_init(c->coef, nullptr, n, 8, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
             }
             const int shift = 2 * (n - G.k_heis);
+            TileSpan span;
+            span.begin(s);
             for (int p = P.heis_pass_begin[sg]; p < P.heis_pass_begin[sg + 1]; ++p) {
                 pp::TileGroups grp{};
                 grp.ngroups = 1;
                 grp.first_block[1] = 1 << shift;
                 grp.first_desc[0] = p;
                 grp.shift[0] = shift;
-                ProfScope ps(PC_TILE, s);
                 HIPCHK(pp::launch_tile_pass(G.hpass, grp, G.k_heis, 8, false, s));
+                span.count();
             }
+            span.end();
         }
         if (sg > 0) HIPCHK(pp::launch_copy_f64(coef, G.ckpt + (size_t)sg * slots, slots, s));
     }
@@ -1647,11 +1696,11 @@ extern "C" pp_status pp_profile_read(pp_kernel_time *out, int32_t max, int32_t *
     double ms[PC_N] = {0};
     int64_t cnt[PC_N] = {0};
     for (const auto &r : g_prof.recs) {
-        HIPCHK(hipEventSynchronize(g_prof.pool[r.second + 1]));
+        HIPCHK(hipEventSynchronize(g_prof.pool[r.start + 1]));
         float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, g_prof.pool[r.second], g_prof.pool[r.second + 1]));
-        ms[r.first] += t;
-        cnt[r.first]++;
+        HIPCHK(hipEventElapsedTime(&t, g_prof.pool[r.start], g_prof.pool[r.start + 1]));
+        ms[r.cls] += t;
+        cnt[r.cls] += r.launches;
     }
     g_prof.recs.clear();
     g_prof.used = 0;
