@@ -101,6 +101,19 @@ def test_density_matrix_paper_chain_workload(api):
     c.close()
 
 
+@pytest.mark.parametrize("n,layers,repeats", [(2, 1000, 1), (3, 100, 1), (4, 1, 1), (2, 50, 100), (3, 50, 10),
+                                               (4, 50, 1)])
+def test_density_matrix_paper_sweep_points(api, n, layers, repeats):
+    """Points of the paper's two timing sweeps (Sec. V): W_chain+ZXZ at
+    n = 2..4, #Layers up to 1000 at #Repeats = 1, #Repeats up to 100 at
+    #Layers = 50."""
+    wc = W.chain_zxz_circuit(seed=1000 * n + layers + repeats, n=n, layers=layers, repeats=repeats)
+    _say(f"density sweep n={n} layers={layers} repeats={repeats} m={wc.m}")
+    c = api.Circuit.from_workload(wc)
+    _check(c.density_matrix().cpu().numpy(), _rho_sv(wc), 1e-11)
+    c.close()
+
+
 def test_density_matrix_clifford_state_is_a_projector(api):
     """H on every qubit: rho = |+...+><+...+|, every entry exactly 2^-n."""
     n = 5
