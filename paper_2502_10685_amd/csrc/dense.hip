@@ -318,6 +318,13 @@ __device__ __forceinline__ void u1_quad(double *v, const double (&m)[9]) {
 // U1 (3x3 map M over X, Y, Z) on one digit of a 16-register block; LO: the
 // lower digit of the pair.
 template <bool LO>
+__device__ __forceinline__ void u1_regs_m(double *v, const double (&m)[9]) {
+    u1_quad<LO, 0>(v, m);
+    u1_quad<LO, 1>(v, m);
+    u1_quad<LO, 2>(v, m);
+    u1_quad<LO, 3>(v, m);
+}
+template <bool LO>
 __device__ __forceinline__ void u1_regs(double *v, const double *M) {
     const double m[9] = {M[0], M[1], M[2], M[3], M[4], M[5], M[6], M[7], M[8]};
     u1_quad<LO, 0>(v, m);
@@ -421,7 +428,7 @@ constexpr LaneOrder lane_order() {
 // letter offsets are constants.
 template <typename T, int K, int BLOCK, int A, int B>
 __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double (*maps)[9], int first, int cnt,
-                                            int tid) {
+                                            int tid, const DOp *gops, const double *gmaps) {
     constexpr int NG = 1 << (2 * (K - 2));
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
     constexpr LaneOrder lo = lane_order<K, A, B>();
@@ -454,8 +461,27 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double 
                                     : __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&ops[first + t])[0]);
             const int kind = w0 & 0xff, da = (w0 >> 8) & 0xff;
             if (kind == DOP_U1) {
-                if (da == A) u1_regs<true>(v, maps[first + t]);
-                else u1_regs<false>(v, maps[first + t]);
+                if constexpr (sizeof(T) == 4) {
+                    // FP32 weights: the map (the same for every lane) comes
+                    // into SGPRs by scalar loads from the global map array
+                    // (gops: the group's ops in global memory, gmaps: the
+                    // map array, both wave-uniform).  The FMAs take it as
+                    // their scalar operand, and the kernel drops under 128
+                    // VGPRs: four waves per SIMD instead of three.  In FP64
+                    // the LDS copy is as fast and the kernel stays at three.
+                    typedef const __attribute__((address_space(4))) uint32_t *CW;
+                    typedef const __attribute__((address_space(4))) double *CD;
+                    const uint32_t mi = ((CW)(gops + first + t))[2];
+                    const CD src = (CD)gmaps + 9ull * mi;
+                    double m[9];
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) m[q] = src[q];
+                    if (da == A) u1_regs_m<true>(v, m);
+                    else u1_regs_m<false>(v, m);
+                } else {
+                    if (da == A) u1_regs<true>(v, maps[first + t]);
+                    else u1_regs<false>(v, maps[first + t]);
+                }
             } else {
                 if (da == A) cx_regs<true>(v);
                 else cx_regs<false>(v);
@@ -468,10 +494,10 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double 
 
 template <typename T, int K, int BLOCK>
 __device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, const double (*maps)[9], int first,
-                                            int cnt, int tid) {
-#define PP_GROUP_CASE(A_, B_)                                                               \
-    case (A_) * 8 + (B_):                                                                  \
-        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, maps, first, cnt, tid); \
+                                            int cnt, int tid, const DOp *gops, const double *gmaps) {
+#define PP_GROUP_CASE(A_, B_)                                                                                \
+    case (A_) * 8 + (B_):                                                                                   \
+        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, maps, first, cnt, tid, gops, gmaps); \
         return;
     switch (a * 8 + b) {
         PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
@@ -487,14 +513,26 @@ __device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops,
 // Applies ops [o0, o1) to an LDS tile of 4^K slots.  For tracked runs it
 // accumulates term updates: every op adds ngates * (strings in the tile
 // before it), and U1 ops that can create strings update that count.
+// A 64-bit value made wave-uniform.  readfirstlane returns a signed int:
+// each half is widened through uint32_t, or a low half with bit 31 set
+// would fill the high half with ones.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 template <typename T, bool TRACK, int K, int BLOCK, int CH = OPCH>
 __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const double *__restrict__ maps, int o0,
                         int o1, long long &tcount, long long &updates, long long *redi, OpCacheN<CH> *oc,
                         bool preloaded = false) {
     const int tid = threadIdx.x;
+    const double *gmaps = (const double *)uniform_u64((uint64_t)maps);
+    const DOp *gops0 = (const DOp *)uniform_u64((uint64_t)ops);
     int cb = o0;
     while (cb < o1) {
         const int cn = (o1 - cb) < CH ? (o1 - cb) : CH;
+        const DOp *gops = gops0 + cb;  // gops[i] is oc->ops[i]
         lds_barrier();
         if (!preloaded) stage_ops<CH>(oc, ops, maps, cb, cn, tid, BLOCK);
         lds_barrier();
@@ -512,7 +550,8 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
             }
             if (kind == DOP_GROUP) {
                 if (i + 1 + ngates > cn) break;  // reload the chunk from this header
-                if constexpr (K >= 2) group_apply<T, K, BLOCK>(lc, a, b, oc->ops, oc->maps, i + 1, ngates, tid);
+                if constexpr (K >= 2)
+                    group_apply<T, K, BLOCK>(lc, a, b, oc->ops, oc->maps, i + 1, ngates, tid, gops, gmaps);
                 i += 1 + ngates;
             } else if (!TRACK && K >= 2 && K <= 7) {
                 // untracked U1 or CX alone: a group sweep of one op over its
@@ -521,7 +560,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
                 const int other = kind == DOP_U1 ? (a == 0 ? 1 : a - 1) : b;
                 if constexpr (K >= 2)
                     group_apply<T, K, BLOCK>(lc, a < other ? a : other, a < other ? other : a, oc->ops, oc->maps, i, 1,
-                                             tid);
+                                             tid, gops, gmaps);
                 ++i;
             } else if (kind == DOP_U1) {
                 const int delta = u1_apply<T, TRACK, K, BLOCK>(lc, lp, a, oc->maps[i], smask, tid);
