@@ -461,27 +461,21 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double 
                                     : __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&ops[first + t])[0]);
             const int kind = w0 & 0xff, da = (w0 >> 8) & 0xff;
             if (kind == DOP_U1) {
-                if constexpr (sizeof(T) == 4) {
-                    // FP32 weights: the map (the same for every lane) comes
-                    // into SGPRs by scalar loads from the global map array
-                    // (gops: the group's ops in global memory, gmaps: the
-                    // map array, both wave-uniform).  The FMAs take it as
-                    // their scalar operand, and the kernel drops under 128
-                    // VGPRs: four waves per SIMD instead of three.  In FP64
-                    // the LDS copy is as fast and the kernel stays at three.
-                    typedef const __attribute__((address_space(4))) uint32_t *CW;
-                    typedef const __attribute__((address_space(4))) double *CD;
-                    const uint32_t mi = ((CW)(gops + first + t))[2];
-                    const CD src = (CD)gmaps + 9ull * mi;
-                    double m[9];
+                // the map (the same for every lane) comes into SGPRs by
+                // scalar loads from the global map array (gops: the group's
+                // ops in global memory, gmaps: the map array, both
+                // wave-uniform) and is the FMAs' scalar operand: nine fewer
+                // LDS reads and about 16 fewer VGPRs than an LDS copy, which
+                // lets the 6-qubit streaming kernel run four waves per SIMD
+                typedef const __attribute__((address_space(4))) uint32_t *CW;
+                typedef const __attribute__((address_space(4))) double *CD;
+                const uint32_t mi = ((CW)(gops + first + t))[2];
+                const CD src = (CD)gmaps + 9ull * mi;
+                double m[9];
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) m[q] = src[q];
-                    if (da == A) u1_regs_m<true>(v, m);
-                    else u1_regs_m<false>(v, m);
-                } else {
-                    if (da == A) u1_regs<true>(v, maps[first + t]);
-                    else u1_regs<false>(v, maps[first + t]);
-                }
+                for (int q = 0; q < 9; ++q) m[q] = src[q];
+                if (da == A) u1_regs_m<true>(v, m);
+                else u1_regs_m<false>(v, m);
             } else {
                 if (da == A) cx_regs<true>(v);
                 else cx_regs<false>(v);
@@ -786,12 +780,13 @@ __device__ __forceinline__ unsigned stream_soff(uint64_t qubits, int r) {
     return (unsigned)deposit_digits(r * BLOCK, qubits, 4, K) * (unsigned)sizeof(T);
 }
 
-// 256 threads for tiles up to 4^6 slots (3 workgroups per CU); 512 threads
-// and one workgroup per CU for 4^7 slots (its LDS tile is 128 KiB in FP64)
+// 256 threads for tiles up to 4^6 slots (four workgroups per CU: at most 128
+// VGPRs, and 4 x 37 KiB of LDS in FP64); 512 threads and one workgroup per
+// CU for 4^7 slots (its LDS tile is 128 KiB in FP64)
 template <int K>
 constexpr int kStreamBlock = K >= 7 ? 512 : 256;
 template <int K>
-constexpr int kStreamWaves = K >= 7 ? 2 : 3;
+constexpr int kStreamWaves = K >= 7 ? 2 : 4;
 
 // ops held per workgroup: every 6-qubit pass of the planner fits (its passes
 // have at most 64 op entries); longer passes reload chunks inside run_ops
@@ -827,9 +822,11 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
 #pragma unroll
         for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
     }
-    // Per tile: ops (unless the descriptor repeats), the next tile's loads,
-    // the ops in LDS, then this tile's stores are issued before the wait for
-    // the next tile's loads, so neither wait covers fresh stores.
+    // Per tile: ops (unless the descriptor repeats), the next tile's early
+    // rows' loads, the ops in LDS, this tile's stores, then (FP64) the late
+    // rows' loads and the wait for all of them.  The early rows' wait does
+    // not cover the fresh stores; the late rows' does (one counter for both),
+    // which the fourth workgroup per CU hides.
     const TilePassDesc *cached = nullptr;  // descriptor whose whole op list is in oc
     long long tcount = 0, updates = 0;
     for (;;) {
@@ -842,12 +839,17 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
         const int nblk = blk + gridDim.x;
         const bool has_next = nblk < total;
         TileLoc nxt = cur;
+        // rows of the next tile loaded while the ops run: all of them in
+        // FP32; half in FP64, where the whole tile in registers would push
+        // the kernel past 128 VGPRs (three waves per SIMD instead of four,
+        // which cost 7 %); the other half is loaded after this tile's stores
+        constexpr int PE = sizeof(T) == 8 ? PER / 2 : PER;
         if (has_next) {
             nxt = locate_tile<T, K, BLOCK>(descs, grp, nblk, tid);
             const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
             const uint64_t qubits = nxt.d->qubits;
 #pragma unroll
-            for (int r = 0; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
+            for (int r = 0; r < PE; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
         }
         run_ops<T, false, K, BLOCK, kStreamOps>(lc, nullptr, cur.d->ops, cur.d->maps, o0, o1, tcount, updates, redi, &oc,
                                                 true);
@@ -862,6 +864,12 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
             for (int r = 0; r < PER; ++r) BufIO<T>::st(rs, cur.voff, stream_soff<T, K, BLOCK>(qubits, r), out[r]);
         }
         if (!has_next) break;
+        if constexpr (PE < PER) {
+            const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
+            const uint64_t qubits = nxt.d->qubits;
+#pragma unroll
+            for (int r = PE; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
+        }
         lds_barrier();  // every thread has read this tile and is done with oc
 #pragma unroll
         for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
