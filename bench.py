@@ -238,27 +238,35 @@ def gradient_leg(api, torch):
 def sparse_leg(api, torch):
     """The sort-merge engine past the dense range (n = 20, 4^n slots): a seeded
     300-gate random circuit (2.66M strings at the end) and the spread circuit
-    (n = 20, RY on 5 qubits: 7,962,624 strings), one evaluation each timed."""
+    (n = 20, RY on 5 qubits: 7,962,624 strings), one evaluation each timed,
+    launched eagerly and replayed as a captured hipGraph."""
     from paper_2502_10685_amd import workloads as W
     cases = [("random n=20 m=300 seed 20", W.random_circuit(np.random.default_rng(20), 20, 300, W.obs_z(20, [0, 1]))),
              ("spread n=20 k=5", W.spread_circuit(20, 20, 5))]
     out = []
     for name, wc in cases:
-        c = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 24)
-        c.evaluate()
-        torch.cuda.synchronize()
-        reps = 5
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            ev = c.evaluate()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        st = c.stats()
-        out.append({"workload": name, "gates": wc.m, "ms": dt * 1e3, "final_terms": int(st["final_terms"]),
-                    "term_updates": int(st["term_updates"]), "passes": int(st["passes"]),
-                    "updates_per_s": st["term_updates"] / dt, "overflow": bool(st["overflow"]),
-                    "expval": float(ev.item())})
-        c.close()
+        row = {"workload": name, "gates": wc.m}
+        for graph in (False, True):
+            c = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 24, use_graph=graph)
+            c.evaluate()
+            torch.cuda.synchronize()
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ev = c.evaluate()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            st = c.stats()
+            if graph:
+                row.update({"ms_graph": dt * 1e3, "updates_per_s_graph": st["term_updates"] / dt,
+                            "expval_graph": float(ev.item())})
+            else:
+                row.update({"ms": dt * 1e3, "final_terms": int(st["final_terms"]),
+                            "term_updates": int(st["term_updates"]), "passes": int(st["passes"]),
+                            "updates_per_s": st["term_updates"] / dt, "overflow": bool(st["overflow"]),
+                            "expval": float(ev.item())})
+            c.close()
+        out.append(row)
     # truncated propagation past the exact method's reach (approximate; the
     # dropped weight bounds the error of <O>)
     wc = W.random_circuit(np.random.default_rng(32), 32, 400, W.obs_z(32, [0, 1]))
@@ -550,8 +558,9 @@ def main():
         log("sparse engine: n = 20")
         res["sparse"] = sparse_leg(api, torch)
         for r in res["sparse"]:
-            log(f"sparse {r['workload']}: {r['ms']:.2f} ms, {r['final_terms']} strings, "
-                f"{r['updates_per_s']:.3e} updates/s")
+            log(f"sparse {r['workload']}: {r['ms']:.2f} ms"
+                + (f" ({r['ms_graph']:.2f} ms as a graph)" if "ms_graph" in r else "")
+                + f", {r['final_terms']} strings, {r['updates_per_s']:.3e} updates/s")
 
     if not args.no_density and args.workload == "batch512":
         log("density matrix (toDM)")
