@@ -324,14 +324,6 @@ __device__ __forceinline__ void u1_regs_m(double *v, const double (&m)[9]) {
     u1_quad<LO, 2>(v, m);
     u1_quad<LO, 3>(v, m);
 }
-template <bool LO>
-__device__ __forceinline__ void u1_regs(double *v, const double *M) {
-    const double m[9] = {M[0], M[1], M[2], M[3], M[4], M[5], M[6], M[7], M[8]};
-    u1_quad<LO, 0>(v, m);
-    u1_quad<LO, 1>(v, m);
-    u1_quad<LO, 2>(v, m);
-    u1_quad<LO, 3>(v, m);
-}
 
 // Ops and their maps are staged through LDS in chunks: one cooperative load
 // per chunk instead of a dependent global load per op.
@@ -344,6 +336,10 @@ struct OpCacheN {
 using OpCache = OpCacheN<OPCH>;
 
 // Stages ops [o0, o0 + cn) and the maps of their U1 ops into an op cache.
+// Group sweeps read the maps by scalar loads from global memory instead;
+// the copy serves the per-op U1 path (tracked runs) and, for the sweeps,
+// brings the maps into L2 before their scalar loads (without it the
+// streaming kernel is 5 % slower).
 // Ops move as raw 16-byte words from the global address space: copied as a
 // struct of bytes they would go through scratch, whose wait covers every
 // outstanding vector load (tile prefetches included).
@@ -427,8 +423,8 @@ constexpr LaneOrder lane_order() {
 // writes the block back once.  Compiled per digit pair, so the sixteen
 // letter offsets are constants.
 template <typename T, int K, int BLOCK, int A, int B>
-__device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double (*maps)[9], int first, int cnt,
-                                            int tid, const DOp *gops, const double *gmaps) {
+__device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, int cnt, int tid, const DOp *gops,
+                                            const double *gmaps) {
     constexpr int NG = 1 << (2 * (K - 2));
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
     constexpr LaneOrder lo = lane_order<K, A, B>();
@@ -487,11 +483,11 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, const double 
 }
 
 template <typename T, int K, int BLOCK>
-__device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, const double (*maps)[9], int first,
-                                            int cnt, int tid, const DOp *gops, const double *gmaps) {
+__device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, int first, int cnt, int tid,
+                                            const DOp *gops, const double *gmaps) {
 #define PP_GROUP_CASE(A_, B_)                                                                                \
     case (A_) * 8 + (B_):                                                                                   \
-        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, maps, first, cnt, tid, gops, gmaps); \
+        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, first, cnt, tid, gops, gmaps); \
         return;
     switch (a * 8 + b) {
         PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
@@ -545,7 +541,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
             if (kind == DOP_GROUP) {
                 if (i + 1 + ngates > cn) break;  // reload the chunk from this header
                 if constexpr (K >= 2)
-                    group_apply<T, K, BLOCK>(lc, a, b, oc->ops, oc->maps, i + 1, ngates, tid, gops, gmaps);
+                    group_apply<T, K, BLOCK>(lc, a, b, oc->ops, i + 1, ngates, tid, gops, gmaps);
                 i += 1 + ngates;
             } else if (!TRACK && K >= 2 && K <= 7) {
                 // untracked U1 or CX alone: a group sweep of one op over its
@@ -553,8 +549,8 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
                 // the conflict-free lane order of the pair
                 const int other = kind == DOP_U1 ? (a == 0 ? 1 : a - 1) : b;
                 if constexpr (K >= 2)
-                    group_apply<T, K, BLOCK>(lc, a < other ? a : other, a < other ? other : a, oc->ops, oc->maps, i, 1,
-                                             tid, gops, gmaps);
+                    group_apply<T, K, BLOCK>(lc, a < other ? a : other, a < other ? other : a, oc->ops, i, 1, tid, gops,
+                                             gmaps);
                 ++i;
             } else if (kind == DOP_U1) {
                 const int delta = u1_apply<T, TRACK, K, BLOCK>(lc, lp, a, oc->maps[i], smask, tid);
