@@ -1226,11 +1226,21 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
                 }
             std::stable_sort(grp.begin(), grp.end(), [&](int a, int b) { return cs[a]->n > cs[b]->n; });
             for (size_t l = 0; l < maxp; ++l) {
+                // within one n, circuits whose pass l holds more ops come
+                // first: workgroups take tiles with a fixed stride, so the
+                // last round of tiles is the light one
+                std::vector<int> order;
+                for (int i : grp)
+                    if (l < cs[i]->h_pass.size()) order.push_back(i);
+                std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                    if (cs[a]->n != cs[b]->n) return cs[a]->n > cs[b]->n;
+                    const pp::TilePassDesc &pa = cs[a]->h_pass[l], &pb = cs[b]->h_pass[l];
+                    return pa.op_end - pa.op_begin > pb.op_end - pb.op_begin;
+                });
                 std::vector<pp::TilePassDesc> td;
                 pp::TileGroups tg{};
                 int run = 0, last_n = -1;
-                for (int i : grp) {
-                    if (l >= cs[i]->h_pass.size()) continue;
+                for (int i : order) {
                     pp::TilePassDesc d = cs[i]->h_pass[l];
                     if (d.n != last_n) {
                         if (tg.ngroups == pp::kMaxTileGroups) {
