@@ -231,6 +231,25 @@ def test_batch_equals_solo_bitwise(api):
         assert abs(v - oracle.expval_sv(w)) <= TOL64
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_batch_equals_solo_bitwise(api, dtype):
+    """The 512-circuit batch: its launches walk several rounds of tiles per
+    workgroup (next-tile prefetch, half of it in FP64; circuits ordered by
+    their pass's op count), while one circuit at a time fits one round.
+    Every output must be identical bit for bit."""
+    import torch
+    circs = _config3()
+    _say(f"config3 batch vs solo {dtype}")
+    objs = [api.Circuit.from_workload(w, dtype=dtype) for w in circs]
+    out = api.evaluate_batch(objs)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    solo = np.array([float(o.evaluate().item()) for o in objs])
+    assert np.array_equal(got.view(np.uint64), solo.view(np.uint64)), int(np.argmax(got != solo))
+    for o in objs:
+        o.close()
+
+
 # ---------------------------------------------------------------- edge cases
 def test_empty_circuit_and_clifford_only(api):
     wc = W.make_circuit(3, (np.zeros(0, np.uint8), np.zeros(0, np.int32), np.zeros(0, np.int32),
