@@ -532,10 +532,23 @@ def main():
             else:
                 api.evaluate_batch(objs32, out32)
         step32()
+        L.profile_enable(True)
+        L.profile_read()
         s32, _ = timed_steps(step32, args.steps, torch)
+        prof32 = L.profile_read()
+        L.profile_enable(False)
         v32 = out32.cpu().numpy()
         res["fp32"] = {"value": u_step * args.steps / s32, "ms_per_step": s32 / args.steps * 1e3,
                        "max_abs_diff_vs_fp64": float(np.max(np.abs(v32 - gpu_vals)))}
+        t32 = prof32.get("tile_pass")
+        if t32 and t32[0]:
+            # the same kernel on FP32 weights: half the algorithmic bytes
+            b32 = dense_bytes(objs32) * args.steps
+            a32 = b32 / (t32[1] * 1e-3) / 1e9
+            res["fp32"]["roofline"] = {
+                "kernel": TILE_KERNEL_NAMES.get(L.tune_get(L.PP_TUNE_TILE_KERNEL, 6), "tile_kernel"),
+                "bound": "hbm", "achieved": a32, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a32 / PEAK_HBM_GBS,
+                "launches": t32[0], "avg_launch_us": t32[1] * 1e3 / t32[0], "alg_bytes_per_launch": b32 / t32[0]}
         log(f"fp32: {s32 / args.steps * 1e3:.2f} ms/step")
         del objs32
 
