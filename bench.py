@@ -403,8 +403,8 @@ def main():
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU path is a "
-              "design only in this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the library has no multi-GPU "
+              "path; how it would shard is described but not implemented", file=sys.stderr)
         return 2
 
     import torch
