@@ -339,6 +339,36 @@ def density_sweep_leg(api, torch):
     return out
 
 
+def stabilizer_order_leg(api, torch):
+    """The stabilizer order of the paper's Sec. II-B: the number of Pauli
+    strings in a generator Z_j evolved forward, U_k Z_j U_k^dag, after the
+    first k gates of the W_chain+ZXZ ansatz (n = 2..4, two layers of one
+    repeat), the largest over j.  A tracked GPU run propagates Z_j backwards
+    through the k gates in reverse order: H and CX are self-inverse, S and
+    its inverse map X and Y into each other alike, and R(-t) splits the
+    same strings as R(t), so the string set has the forward set's size
+    (zero weights are kept)."""
+    from paper_2502_10685_amd import workloads as W
+    out = []
+    for n in (2, 3, 4):
+        wc = W.chain_zxz_circuit(seed=n, n=n, layers=2, repeats=1)
+        counts = []
+        for k in range(wc.m + 1):
+            best = 0
+            for j in range(n):
+                rev = W.make_circuit(n, (np.ascontiguousarray(wc.op[:k][::-1]), np.ascontiguousarray(wc.q0[:k][::-1]),
+                                         np.ascontiguousarray(wc.q1[:k][::-1]),
+                                         np.ascontiguousarray(wc.param[:k][::-1])),
+                                     wc.n_params, W.obs_z(n, [j]), wc.theta)
+                c = api.Circuit.from_workload(rev, track=True)
+                c.evaluate()
+                best = max(best, int(c.stats()["final_terms"]))
+                c.close()
+            counts.append(best)
+        out.append({"n": n, "gates": list(range(wc.m + 1)), "max_order": counts, "bound": 4 ** n - 1})
+    return out
+
+
 def cpu_baseline(circs, gpu_vals, seconds, updates):
     """The oracle's scalar propagator on a bounded sample of the workload: every
     8th circuit whose estimated cost still fits the time budget."""
@@ -580,6 +610,9 @@ def main():
         res["density_matrix"] = density_leg(api, torch)
         for r in res["density_matrix"]:
             log(f"toDM {r['workload']}: {r['ms']:.3f} ms (|Tr rho - 1| {r['trace_minus_1']:.1e})")
+        res["stabilizer_order"] = stabilizer_order_leg(api, torch)
+        for r in res["stabilizer_order"]:
+            log(f"stabilizer order n={r['n']}: {r['max_order']} (bound {r['bound']})")
         res["density_sweep"] = density_sweep_leg(api, torch)
         for sweep in ("layers", "repeats"):
             pts = [r for r in res["density_sweep"] if r["sweep"] == sweep]

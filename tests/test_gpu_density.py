@@ -114,6 +114,28 @@ def test_density_matrix_paper_sweep_points(api, n, layers, repeats):
     c.close()
 
 
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_stabilizer_order_matches_forward_oracle(api, n):
+    """The stabilizer order (Sec. II-B) of U_k Z_j U_k^dag after the first k
+    gates of the W_chain+ZXZ ansatz: a tracked GPU run of Z_j backwards
+    through the k gates reversed has exactly the size of the oracle's
+    forward (Schroedinger) set."""
+    wc = W.chain_zxz_circuit(seed=n, n=n, layers=2, repeats=1)
+    _say(f"stabilizer order n={n} m={wc.m}")
+    for k in range(0, wc.m + 1, 3):
+        for j in range(n):
+            fwd = W.make_circuit(n, (wc.op[:k], wc.q0[:k], wc.q1[:k], wc.param[:k]), wc.n_params,
+                                 W.obs_z(n, [j]), wc.theta)
+            want = len(oracle.propagate(fwd, direction=1).x)
+            rev = W.make_circuit(n, (np.ascontiguousarray(wc.op[:k][::-1]), np.ascontiguousarray(wc.q0[:k][::-1]),
+                                     np.ascontiguousarray(wc.q1[:k][::-1]), np.ascontiguousarray(wc.param[:k][::-1])),
+                                 wc.n_params, W.obs_z(n, [j]), wc.theta)
+            c = api.Circuit.from_workload(rev, track=True)
+            c.evaluate()
+            assert int(c.stats()["final_terms"]) == want, (k, j)
+            c.close()
+
+
 def test_density_matrix_clifford_state_is_a_projector(api):
     """H on every qubit: rho = |+...+><+...+|, every entry exactly 2^-n."""
     n = 5
