@@ -63,3 +63,26 @@ def test_profile_counts_tile_passes(api):
     assert L.profile_read() == {}
     for c in cs:
         c.close()
+
+
+def test_profile_records_no_tile_pass_without_passes(api):
+    """A tiled circuit with no gates has no tile pass: the timing records
+    none (the bracketing events are only kept around launches)."""
+    import torch
+    from paper_2502_10685_amd import _lib as L
+    print("profile: n=8, no gates", flush=True)
+    wc = W.make_circuit(8, W._arrays([], [], [], []), 0, W.obs_z(8, [0, 1]), np.zeros(0))
+    c = api.Circuit.from_workload(wc)
+    assert float(c.evaluate().item()) == 1.0  # <0|Z0 Z1|0>
+    torch.cuda.synchronize()
+    L.profile_enable(True)
+    try:
+        L.profile_read()
+        ev = float(c.evaluate().item())
+        torch.cuda.synchronize()
+        prof = L.profile_read()
+    finally:
+        L.profile_enable(False)
+    assert ev == 1.0
+    assert "tile_pass" not in prof
+    c.close()
