@@ -98,15 +98,18 @@ def count_updates(api, circs, dtype):
 
 def serve(api, lam, count, budget, max_active):
     """Poisson arrivals at rate lam (seeded) of random circuits n ~ U{4..12},
-    m log-uniform in [1k, 60k]; submit at arrival time, poll completions."""
+    m log-uniform in [1k, 60k]; submit at arrival time, poll completions.
+    Afterwards every served value is compared bit for bit with the same
+    circuit evaluated alone (the oracle leg checks them against the state
+    vector)."""
     from paper_2502_10685_amd import workloads as W
+    import torch
     reqs = W.config5_requests(seed=5, lam=lam, count=count)
     arrivals = np.array([a for a, _ in reqs])
     ws = [w for _, w in reqs]
     U, _ = count_updates(api, ws, "f64")
     circs = [api.Circuit.from_workload(w) for w in ws]
     srv = api.Server(mem_budget_bytes=budget, max_active=max_active)
-    import torch
     torch.cuda.synchronize()
     lat, done_at, vals = {}, {}, {}
     t0 = time.perf_counter()
@@ -129,14 +132,25 @@ def serve(api, lam, count, budget, max_active):
             time.sleep(2e-4)
     span = max(done_at.values())
     cnt = srv.counters()
+    held, peak = srv.pool_bytes()
     srv.close()
+    served = np.array([vals[j] for j in range(count)])
+    solo = np.empty(count)
+    for j, w in enumerate(ws):
+        c = api.Circuit.from_workload(w)
+        solo[j] = float(c.evaluate().item())
+        c.close()
+    mismatch = int(np.sum(served != solo))
     lats = np.array([lat[j] for j in range(count)]) * 1e-3
-    return {"lambda_per_s": lam, "requests": count, "span_s": span,
-            "offered_updates_per_s": float(U.sum() / max(arrivals[-1], 1e-9)),
-            "updates_per_s": float(U.sum() / span), "circuits_per_s": count / span,
-            "latency_ms": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99))},
-            "term_updates": int(U.sum()), "server": cnt,
-            "n_range": [int(min(w.n for w in ws)), int(max(w.n for w in ws))]}
+    rec = {"lambda_per_s": lam, "requests": count, "span_s": span,
+           "offered_updates_per_s": float(U.sum() / max(arrivals[-1], 1e-9)),
+           "updates_per_s": float(U.sum() / span), "circuits_per_s": count / span,
+           "latency_ms": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99))},
+           "term_updates": int(U.sum()), "server": cnt,
+           "pool_bytes_peak": int(peak), "budget_bytes": int(budget),
+           "served_vs_solo_bitwise_mismatches": mismatch,
+           "n_range": [int(min(w.n for w in ws)), int(max(w.n for w in ws))]}
+    return rec, ws, served
 
 
 def timed_steps(fn, steps, torch):
@@ -186,13 +200,15 @@ def dense_bytes(objs):
 
 def gradient_leg(api, torch):
     """n = 8, HEA-40, TFIM (960 parameters): the adjoint gradient (checkpoint
-    every 5 layers) against the parameter-shift gradient, whose 1,920 shifted
-    evaluations run as one parameter sweep."""
+    every 5 layers, eager and replayed as a graph) against the
+    parameter-shift gradient (pp_psr_gradient: its 1,920 shifted evaluations
+    run as one parameter sweep, the combine on the device).  Returns the
+    timing record and the gradients, which the oracle leg checks."""
     from paper_2502_10685_amd import workloads as W
     wc = W.config4()
     c = api.Circuit.from_workload(wc)
     ev, g_adj = c.gradient(5 * 32)
-    g_psr = c.psr_gradient(wc.theta).numpy()
+    g_psr = c.psr_gradient()
     torch.cuda.synchronize()
     reps = 5
     t0 = time.perf_counter()
@@ -209,30 +225,24 @@ def gradient_leg(api, torch):
     torch.cuda.synchronize()
     t_adj_graph = (time.perf_counter() - t0) / reps
     cg.close()
-    pc, rot = c._psr
-    base = wc.theta[wc.param[rot]]
-    th = np.repeat(base[None, :], 2 * rot.size, axis=0)
-    for j in range(rot.size):
-        th[2 * j, j] += math.pi / 2
-        th[2 * j + 1, j] -= math.pi / 2
-    th_dev = torch.tensor(th, device="cuda")
-    out = torch.empty(th.shape[0], dtype=torch.float64, device="cuda")
-    pc.evaluate_thetas(th_dev, out=out)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        pc.evaluate_thetas(th_dev, out=out)
+        c.psr_gradient()
     torch.cuda.synchronize()
     t_psr = (time.perf_counter() - t0) / reps
+    n_psr = 2 * int(np.sum(wc.op >= 3))
     u_eval = int(count_updates(api, [wc], "f64")[0][0])
+    g_adj = g_adj.cpu().numpy()
+    g_psr = g_psr.cpu().numpy()
     c.close()
-    return {"workload": "n=8 HEA-40 (1280 gates, 960 theta), TFIM, FP64",
-            "adjoint_ms": t_adj * 1e3, "adjoint_graph_ms": t_adj_graph * 1e3,
-            "psr_sweep_ms": t_psr * 1e3, "psr_evaluations": int(th.shape[0]),
-            "psr_evaluations_per_s": th.shape[0] / t_psr,
-            "psr_updates_per_s": th.shape[0] * u_eval / t_psr,
-            "adjoint_speedup_vs_psr": t_psr / t_adj,
-            "max_abs_adjoint_minus_psr": float(np.max(np.abs(g_adj.cpu().numpy() - g_psr)))}
+    rec = {"workload": "n=8 HEA-40 (1280 gates, 960 theta), TFIM, FP64",
+           "adjoint_ms": t_adj * 1e3, "adjoint_graph_ms": t_adj_graph * 1e3,
+           "psr_ms": t_psr * 1e3, "psr_evaluations": n_psr,
+           "psr_evaluations_per_s": n_psr / t_psr,
+           "psr_updates_per_s": n_psr * u_eval / t_psr,
+           "adjoint_speedup_vs_psr": t_psr / t_adj,
+           "max_abs_adjoint_minus_psr": float(np.max(np.abs(g_adj - g_psr)))}
+    return rec, {"circuit": wc, "adjoint": g_adj, "psr": g_psr, "expval": float(ev.item())}
 
 
 def sparse_leg(api, torch):
@@ -369,44 +379,92 @@ def stabilizer_order_leg(api, torch):
     return out
 
 
-def cpu_baseline(circs, gpu_vals, seconds, updates):
-    """The oracle's scalar propagator on a bounded sample of the workload: every
-    8th circuit whose estimated cost still fits the time budget."""
-    import oracle
-    done_u, spent, maxerr, names = 0, 0.0, 0.0, []
-    order = list(range(0, len(circs), 8)) if len(circs) > 1 else [0]
-    rate_guess = 5.0e6  # updates/s of the oracle on one core, for budgeting only
-    picked = [i for i in order if updates[i] / rate_guess <= seconds]
-    if not picked:
-        picked = [min(order, key=lambda i: updates[i])]
-    for i in picked:
-        if spent > 0 and spent + updates[i] / rate_guess > seconds:
-            continue
-        t0 = time.perf_counter()
-        r = oracle.propagate(circs[i])
-        dt = time.perf_counter() - t0
-        spent += dt
-        done_u += r.updates
-        maxerr = max(maxerr, abs(r.expval - gpu_vals[i]))
-        names.append(i)
-        if spent >= seconds:
-            break
-    # context: the oracle's FP64 state vector on the same sample (the method
-    # works in the 4^n Pauli space; a state vector needs 2^n amplitudes)
-    t0 = time.perf_counter()
-    sv_err = 0.0
-    for i in names:
-        sv_err = max(sv_err, abs(oracle.expval_sv(circs[i]) - gpu_vals[i]))
-    sv_dt = time.perf_counter() - t0
-    return {"value": done_u / spent if spent > 0 else None, "unit": "Pauli-term updates/s",
-            "cores": 1, "kind": "oracle",
-            "statevector_circuits_per_s": len(names) / sv_dt if sv_dt > 0 else None,
-            "max_abs_err_gpu_vs_statevector": sv_err,
-            "sample": (f"scalar Pauli propagator (C, merge after every gate, 1 thread) on {len(names)} "
-                       f"of the workload's circuits (every 8th that fits a {seconds:.0f}s budget: "
-                       f"{names[:10]}{'...' if len(names) > 10 else ''}), "
-                       f"{done_u:.3e} updates in {spent:.1f}s"),
-            "max_abs_err_vs_gpu": maxerr}
+# Gates of each sampled circuit the timed oracle run propagates, per n: the
+# whole circuit for n <= 6, else its last L gates (the first L a Heisenberg
+# propagation meets), about 6e7 term updates each once the set is saturated
+ORACLE_SUFFIX = {7: 4000, 8: 1000, 9: 400, 10: 280}
+
+
+def cpu_baseline(circs, updates, checks):
+    """The CPU oracle on the host's cores (one process per circuit).
+
+    Timing: the scalar Pauli propagator on every 8th circuit of the workload
+    (the whole circuit for n <= 6, else a suffix sized by ORACLE_SUFFIX),
+    run across all worker processes at once: `value` is the measured
+    aggregate rate.  Per-n single-process rates give an extrapolated time for
+    the whole batch (labelled as such).
+
+    Errors: every GPU result of the benchmark against the oracle's FP64 state
+    vector (all batch outputs in FP64 and FP32, every served value) and the
+    adjoint and parameter-shift gradients against the oracle's
+    parameter-shift rule."""
+    from oracle import pool
+    workers = pool.default_workers()
+    sample = list(range(0, len(circs), 8)) if len(circs) > 1 else [0]
+    jobs = [("propagate", circs[i], ORACLE_SUFFIX.get(circs[i].n, circs[i].m)) for i in sample]
+    res, wall, workers = pool.run(jobs, workers)
+    done_u = sum(r["updates"] for r in res)
+    busy = sum(r["seconds"] for r in res)
+    per_n = {}
+    for i, r in zip(sample, res):
+        d = per_n.setdefault(int(circs[i].n), {"circuits": 0, "updates": 0, "seconds": 0.0})
+        d["circuits"] += 1
+        d["updates"] += int(r["updates"])
+        d["seconds"] += r["seconds"]
+    for d in per_n.values():
+        d["updates_per_s_one_process"] = d["updates"] / d["seconds"] if d["seconds"] > 0 else None
+    est = 0.0
+    for w, u in zip(circs, updates):
+        rate = per_n.get(int(w.n), {}).get("updates_per_s_one_process")
+        if rate is None:  # an n the sample missed: the nearest sampled n
+            near = min(per_n, key=lambda k: abs(k - int(w.n)))
+            rate = per_n[near]["updates_per_s_one_process"]
+        est += float(u) / rate
+    out = {"value": done_u / wall, "unit": "Pauli-term updates/s", "cores": workers, "kind": "oracle",
+           "host_cpus": os.cpu_count(), "cpu_model": pool.cpu_model(),
+           "sample": (f"scalar Pauli propagator (C, merge after every gate), one process per circuit on "
+                      f"{workers} worker processes, on every 8th circuit of the workload ({len(sample)} circuits; "
+                      f"circuits with n >= 7 timed on their last {ORACLE_SUFFIX} gates): "
+                      f"{done_u:.3e} updates in {wall:.1f} s wall ({busy:.1f} s summed over processes)"),
+           "per_n": {str(k): per_n[k] for k in sorted(per_n)},
+           "batch_seconds_extrapolated": est / workers,
+           "batch_updates_per_s_extrapolated": float(np.sum(updates)) / (est / workers),
+           "extrapolation": ("whole batch from the per-n one-process rates, split evenly over the worker "
+                             "processes (independent circuits)")}
+    # every GPU result against the oracle's state vector / parameter-shift rule
+    cjobs, slots = [], []
+    for i, w in enumerate(circs):
+        cjobs.append(("sv", w, None))
+        slots.append(("batch", i))
+    for k, (ws, _) in enumerate(checks.get("served", [])):
+        for j, w in enumerate(ws):
+            cjobs.append(("sv", w, None))
+            slots.append(("served", (k, j)))
+    if "gradient" in checks:
+        cjobs.append(("psr", checks["gradient"]["circuit"], None))
+        slots.append(("psr", 0))
+    cres, cwall, _ = pool.run(cjobs, workers)
+    sv_batch = np.array([r["expval"] for (kind, _), r in zip(slots, cres) if kind == "batch"])
+    errs = {"checked_on": f"{len(cjobs)} oracle runs in {cwall:.1f} s wall on {workers} processes"}
+    errs["batch_fp64_max_abs_vs_statevector"] = float(np.max(np.abs(checks["batch_f64"] - sv_batch)))
+    if checks.get("batch_f32") is not None:
+        errs["batch_fp32_max_abs_vs_statevector"] = float(np.max(np.abs(checks["batch_f32"] - sv_batch)))
+    if checks.get("served"):
+        sv_served = {}
+        for (kind, key), r in zip(slots, cres):
+            if kind == "served":
+                sv_served[key] = r["expval"]
+        errs["served_max_abs_vs_statevector"] = [
+            float(max(abs(vals[j] - sv_served[(k, j)]) for j in range(len(vals))))
+            for k, (_, vals) in enumerate(checks["served"])]
+        errs["served_requests_checked"] = int(sum(len(v) for _, v in checks["served"]))
+    if "gradient" in checks:
+        g_orc = [r["grad"] for (kind, _), r in zip(slots, cres) if kind == "psr"][0]
+        g = checks["gradient"]
+        errs["gradient_adjoint_max_abs_vs_oracle_psr"] = float(np.max(np.abs(g["adjoint"] - g_orc)))
+        errs["gradient_psr_max_abs_vs_oracle_psr"] = float(np.max(np.abs(g["psr"] - g_orc)))
+    out["errors"] = errs
+    return out
 
 
 def main():
@@ -418,7 +476,6 @@ def main():
     ap.add_argument("--dtype", default="f64")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
@@ -488,6 +545,7 @@ def main():
     prof = L.profile_read()
     L.profile_enable(False)
     gpu_vals = out.cpu().numpy().copy()
+    checks = {"batch_f64": gpu_vals}  # GPU results the oracle leg checks
     value = u_step * args.steps / total_s
     log(f"batched: {total_s / args.steps * 1e3:.2f} ms/step, {value:.4e} updates/s")
 
@@ -568,6 +626,7 @@ def main():
         prof32 = L.profile_read()
         L.profile_enable(False)
         v32 = out32.cpu().numpy()
+        checks["batch_f32"] = v32
         res["fp32"] = {"value": u_step * args.steps / s32, "ms_per_step": s32 / args.steps * 1e3,
                        "max_abs_diff_vs_fp64": float(np.max(np.abs(v32 - gpu_vals)))}
         t32 = prof32.get("tile_pass")
@@ -586,16 +645,17 @@ def main():
         res["serving"] = []
         for lam in (100.0, 1000.0):
             log(f"serving lambda={lam:.0f}/s")
-            sv = serve(api, lam, args.serve_requests, budget=64 << 30, max_active=64)
+            sv, sws, svals = serve(api, lam, args.serve_requests, budget=64 << 30, max_active=64)
+            checks.setdefault("served", []).append((sws, svals))
             log(f"serving lambda={lam:.0f}: p50 {sv['latency_ms']['p50']:.1f} ms, p99 "
                 f"{sv['latency_ms']['p99']:.1f} ms, {sv['updates_per_s']:.3e} updates/s")
             res["serving"].append(sv)
 
     if not args.no_grad and args.workload == "batch512":
         log("gradient: adjoint vs parameter-shift sweep")
-        res["gradient"] = gradient_leg(api, torch)
+        res["gradient"], checks["gradient"] = gradient_leg(api, torch)
         log(f"gradient: adjoint {res['gradient']['adjoint_ms']:.2f} ms, psr sweep "
-            f"{res['gradient']['psr_sweep_ms']:.2f} ms")
+            f"{res['gradient']['psr_ms']:.2f} ms")
 
     if not args.no_sparse and args.workload == "batch512":
         log("sparse engine: n = 20")
@@ -621,7 +681,7 @@ def main():
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(circs, gpu_vals, args.cpu_seconds, U)
+        res["cpu_baseline"] = cpu_baseline(circs, U, checks)
     print(json.dumps(res), flush=True)
     return 0
 

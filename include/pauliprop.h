@@ -26,7 +26,8 @@
  * Asynchrony: functions taking a stream enqueue work on that HIP stream
  * (a hipStream_t passed as void*, NULL = the null stream) and return; device
  * outputs are valid once the stream has reached that point.  Functions that
- * return host data (pp_get_terms, pp_get_stats) synchronize the stream.
+ * return host data synchronize: pp_get_terms its stream, pp_get_stats the
+ * device.  A circuit keeps no stream handle of a past call.
  * Threading: one circuit must not be used by two threads at once; distinct
  * circuits are independent.
  */
@@ -119,22 +120,57 @@ typedef struct pp_kernel_time {
     double total_ms;    /* sum of event-measured durations */
 } pp_kernel_time;
 
+/* ------------------------------------------------------- device memory */
+/* Where the library's device buffers come from (the per-circuit weights,
+ * schedules and scratch, the server's pool).  alloc(bytes, stream, user)
+ * returns device memory of at least `bytes` bytes usable on any stream once
+ * it returns, or NULL on failure (the calling entry point then returns
+ * PP_ERR_NOMEM and leaves its object usable: a later call with memory
+ * available succeeds); `stream` is the stream of the first use or NULL.
+ * free(ptr, bytes, stream, user) takes back a block of this allocator; the
+ * library synchronizes the device first, so no enqueued work still uses it.
+ * Both may be called from the library's own threads (the serving loop and
+ * its preparation threads). */
+typedef struct pp_allocator {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *user);
+    void *user;
+} pp_allocator;
+
+/* Installs the allocator for every later device allocation (a copy of *a is
+ * kept); NULL restores the default, the stream-ordered pool (hipMallocAsync
+ * on an internal stream, synchronized before the buffer is handed out).  A
+ * block is always returned to the allocator that made it.  The Python
+ * binding installs torch's caching allocator.  PP_ERR_INVALID if alloc or
+ * free is NULL.  This is the instructor/gate boundary of Sec. III-A with the
+ * device memory owned by the framework above it. */
+PP_API pp_status pp_set_allocator(const pp_allocator *a);
+
+/* Bytes and blocks of device memory the library holds right now (all
+ * circuits, servers and scratch of the process). */
+PP_API pp_status pp_memory_in_use(int64_t *bytes, int64_t *blocks);
+
 /* Library version string; never NULL. */
 PP_API const char *pp_version(void);
 
 /* Message of the last failure on the calling thread ("" if none). */
 PP_API const char *pp_last_error(void);
 
-/* Creates an empty circuit on the current HIP device.  n_qubits in [1, 64]
- * (DENSE additionally needs 4^n slots in memory).  *out receives the handle;
- * release it with pp_circuit_destroy. */
+/* Creates an empty circuit on the current HIP device: n qubits starting in
+ * |0...0> (Sec. II-A: the initial state is stabilized by the Z_j).  n_qubits
+ * in [1, 64] (DENSE additionally needs 4^n slots in memory).  *out receives
+ * the handle; release it with pp_circuit_destroy.  No device memory is
+ * allocated yet. */
 PP_API pp_status pp_circuit_create(int32_t n_qubits, pp_dtype dtype, pp_engine engine, pp_circuit **out);
 
 /* Releases the circuit and every device buffer it owns.  NULL-safe.  The
  * caller must make sure no enqueued work still uses it. */
 PP_API void pp_circuit_destroy(pp_circuit *c);
 
-/* Loads the gate list (host arrays of length m, copied during the call).
+/* Loads the gate list (host arrays of length m, copied during the call):
+ * the instructors {gate, wire, theta} of Sec. III-A in application order.
+ * A device array for the angles is allocated (PP_ERR_NOMEM on failure, the
+ * circuit keeping its previous gates).
  * op[g] is a pp_op; q0[g] the qubit (CX control); q1[g] the CX target, else
  * ignored; param[g] in [0, n_params) for rotations, ignored otherwise.
  * Errors: PP_ERR_INVALID for an unknown op, a qubit outside [0, n),
@@ -142,32 +178,43 @@ PP_API void pp_circuit_destroy(pp_circuit *c);
 PP_API pp_status pp_circuit_load_gates(pp_circuit *c, int64_t m, const uint8_t *op, const int32_t *q0,
                                 const int32_t *q1, const int32_t *param, int32_t n_params);
 
-/* Sets the n_params angles.  on_device = 0: theta is a host array (copied
+/* Sets the n_params angles of the parameterized gates (the theta of the
+ * PQC, Sec. I).  on_device = 0: theta is a host array (copied
  * before return); 1: theta is a device array read by the next evaluations
  * on `stream` (it must stay valid until they ran).  Non-finite angles are
  * not checked; they propagate NaN. */
 PP_API pp_status pp_circuit_set_theta(pp_circuit *c, const double *theta, int32_t on_device, void *stream);
 
-/* Sets the observable O = sum_k coeff[k] P(x[k], z[k]) (host arrays, copied).
- * Bits at or above n must be zero.  Repeated strings are summed. */
+/* Sets the observable O = sum_k coeff[k] P(x[k], z[k]) (host arrays, copied):
+ * a real-weighted sum of Pauli strings, the form every propagated operator
+ * keeps (Sec. II-A, the lambda_j P_j of the generator expansion).  Bits at
+ * or above n must be zero (PP_ERR_INVALID).  Repeated strings are summed. */
 PP_API pp_status pp_circuit_set_observable(pp_circuit *c, int64_t n_terms, const uint64_t *x,
                                     const uint64_t *z, const double *coeff);
 
-/* Sets a pp_option; takes effect at the next evaluation. */
+/* Sets a pp_option; takes effect at the next evaluation.  PP_ERR_INVALID
+ * for an unknown key or a value out of range (the circuit unchanged). */
 PP_API pp_status pp_circuit_set_option(pp_circuit *c, pp_option key, int64_t value);
 
-/* Enqueues one evaluation of <O>; d_expval is caller-owned device memory for
- * one double.  PP_ERR_STATE if gates, theta or the observable are missing. */
+/* Enqueues one evaluation of <O> = <0...0| U^dag O U |0...0> (measurement
+ * of Sec. II-A from the propagated strings: only strings of I and Z have a
+ * nonzero expectation in |0...0>); d_expval is caller-owned device memory
+ * for one double.  PP_ERR_STATE if gates, theta or the observable are
+ * missing; PP_ERR_NOMEM if the first evaluation's buffers cannot be
+ * allocated (the circuit stays usable). */
 PP_API pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval);
 
-/* Evaluates `count` independent circuits in batched launches on `stream`:
- * circuits that fit one workgroup's LDS run one per workgroup in a single
- * launch per size class, larger ones share multi-circuit tiled passes.
- * d_expvals: caller-owned device array of `count` doubles, in input order.
- * Each circuit's result is bit-identical to its own pp_evaluate. */
+/* Evaluates `count` independent circuits in batched launches on `stream`
+ * (the independent units of Sec. IV run side by side; the PSR of Sec. I
+ * needs 2m evaluations per gradient): circuits that fit one workgroup's LDS
+ * run one per workgroup in a single launch per size class, larger ones share
+ * multi-circuit tiled passes.  d_expvals: caller-owned device array of
+ * `count` doubles, in input order.  Each circuit's result is bit-identical
+ * to its own pp_evaluate.  PP_ERR_INVALID if a circuit appears twice (the
+ * launches would update its one weight array from two places). */
 PP_API pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, void *stream, double *d_expvals);
 
-/* Parameter sweep (the parameter-shift variants of a training step, a scan
+/* Parameter sweep (the 2m parameter-shift evaluations of Sec. I, a scan
  * over theta): enqueues <O> of circuit c at `count` parameter vectors.
  * thetas: count x n_params doubles, row-major, host memory (on_device = 0,
  * copied before return) or device memory (on_device = 1, read on `stream`).
@@ -184,10 +231,28 @@ PP_API pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const double *
 /* Enqueues <O> and its gradient with respect to theta (adjoint method on the
  * DENSE engine): d_expval one double, d_grad n_params doubles (caller-owned
  * device memory; contributions of gates sharing a parameter are summed).
- * checkpoint_every_gates > 0 stores the propagated set every that many gates
- * and recomputes inside each segment; 0 picks a default. */
+ * The gradient the parameter-shift rule of Sec. I gives with 2m evaluations
+ * comes from two sweeps: the observable's weights c_k (Heisenberg picture)
+ * and the state's Pauli coefficients r_k (the density operator as a sum over
+ * Pauli strings, eqs. (2)-(3)) are joined at every rotation,
+ * d<O>/d theta_k = c_k^T A_sigma r_k.  checkpoint_every_gates > 0 stores
+ * the propagated set every that many gates and recomputes inside each
+ * segment; 0 picks a default.  FP64 only. */
 PP_API pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint_every_gates, double *d_expval,
                       double *d_grad);
+
+/* Parameter-shift gradient (Sec. I: each rotation's derivative is half the
+ * difference of two evaluations at its angle +- pi/2, exact for generators
+ * with eigenvalues +-1/2): enqueues the 2R shifted evaluations of the R
+ * rotation gates as one parameter sweep (pp_evaluate_thetas) of a private
+ * copy of the circuit in which every rotation has a parameter of its own,
+ * and sums the halved differences per parameter in gate order, all on the
+ * device.  d_grad: caller-owned device array of n_params doubles.  The
+ * private copy, its 2R x R shifted sets and its sweep buffers (2R x 4^n
+ * weights for tiled circuits) stay allocated with c.  DENSE engine without
+ * term tracking (else PP_ERR_STATE); PP_ERR_CAPACITY when 2R^2 exceeds
+ * 2^27 doubles. */
+PP_API pp_status pp_psr_gradient(pp_circuit *c, void *stream, double *d_grad);
 
 /* Density matrix rho = U(theta) |0...0><0...0| U(theta)^dag (the paper's toDM
  * task; density operator as a sum over the stabilizer group, eq. (3), decoded
@@ -221,7 +286,8 @@ PP_API pp_status pp_circuit_set_truncation(pp_circuit *c, double min_abs_coeff, 
 PP_API pp_status pp_get_truncation(pp_circuit *c, void *stream, double *dropped_abs);
 
 /* Copies the final string set of the last evaluation to host arrays in
- * canonical order (by z, then x), synchronizing `stream`.  DENSE with
+ * canonical order (by z, then x), synchronizing `stream`: the reduced
+ * weighted string set of Sec. III-B (Examples 3 and 4).  DENSE with
  * PP_OPT_TRACK_TERMS = 1 for that evaluation returns the structural set (exact
  * zero weights included, as the paper's expand/reduce keeps them); without it,
  * the strings whose final weight is nonzero (tiled circuits only: an untracked
@@ -232,29 +298,50 @@ PP_API pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uin
                        double *coeff, int64_t *n_out);
 
 /* Fills *out with the statistics of the last evaluation (synchronizes the
- * stream of that evaluation). */
+ * device; the evaluation's stream may no longer exist): the work of the Map stage of Sec. IV-B as term
+ * updates, passes and algorithmic bytes. */
 PP_API pp_status pp_get_stats(pp_circuit *c, pp_stats *out);
 
 /* ----------------------------------------------------------- serving */
 typedef struct pp_server pp_server;
 
-/* Starts a serving loop on its own host thread and HIP streams of the
- * current device.  Requests are admitted in arrival order while at most
- * max_active are in flight and the sum of their term-buffer footprints
- * (4^n weights for DENSE, the term capacity for SPARSE) stays within
- * mem_budget_bytes.  Admitted requests share work: every loop iteration
- * issues one batched tile pass holding the next pass of every active tiled
- * request (requests join and leave between iterations), while circuits that
- * fit one workgroup's LDS run whole beside the passes: the pending ones are
- * launched together (one workgroup each) on whichever of three side streams
- * is idle.  Each request's result is bit-identical to its own pp_evaluate. */
+/* Serving (no counterpart in the paper, whose PQC training loop of Sec. I
+ * evaluates many independent circuits: here they arrive one by one).
+ *
+ * Starts a serving loop on its own host thread and HIP streams of the
+ * current device, with four preparation threads that build and upload each
+ * request's schedule as it is submitted.  Prepared requests are admitted in
+ * submission order while at most max_active are in flight and the sum of
+ * their footprints (4^n weights for tiled DENSE requests, the term capacity
+ * for SPARSE or tracked ones, none for LDS-resident ones) stays within
+ * mem_budget_bytes.  Tiled DENSE requests run in weight buffers of the
+ * server's pool, returned at completion and reused; the pool (buffers in
+ * use and free) never exceeds mem_budget_bytes, so the budget bounds the
+ * device memory of the served weights.  Admitted requests share work: every
+ * loop iteration issues one batched tile pass per (tile size, weight type)
+ * holding the next pass of every active tiled request (requests join and
+ * leave between iterations), while circuits that fit one workgroup's LDS run
+ * whole beside the passes: the pending ones are launched together (one
+ * workgroup each) on whichever of three side streams is idle.  Each
+ * request's result is bit-identical to its own pp_evaluate.  Device buffers
+ * come from the allocator of pp_set_allocator. */
 PP_API pp_status pp_server_create(int64_t mem_budget_bytes, int32_t max_active, pp_server **out);
+
+/* Bounds the requests submitted and not yet admitted: with max_queued > 0
+ * pp_server_submit returns PP_ERR_BUSY (nothing queued) while that many
+ * wait; 0 (the default) queues without bound. */
+PP_API pp_status pp_server_set_queue_limit(pp_server *s, int64_t max_queued);
 
 /* Queues an evaluation of circuit c (gates, theta and observable set) and
  * returns its ticket.  The server owns c until the request is done: the
- * caller must not use or destroy it before pp_server_poll reports done.
- * PP_ERR_CAPACITY if c alone exceeds the memory budget; PP_ERR_STATE after
- * pp_server_destroy has begun. */
+ * caller must not use, change or destroy it before pp_server_poll reports
+ * done.  The work is ordered after c's last pp_circuit_set_theta upload on
+ * whatever stream it was made.  A served tiled DENSE circuit keeps no final
+ * weights (pp_get_terms then gives PP_ERR_STATE).  Errors: PP_ERR_CAPACITY
+ * if c alone exceeds the memory budget; PP_ERR_INVALID if c was submitted
+ * and is not done yet; PP_ERR_BUSY if the queue limit is reached;
+ * PP_ERR_STATE after pp_server_destroy has begun.  Planning errors are
+ * reported by pp_server_poll. */
 PP_API pp_status pp_server_submit(pp_server *s, pp_circuit *c, int64_t *ticket);
 
 /* Non-blocking status of a ticket: *done = 1 once the result is on the
@@ -266,15 +353,21 @@ PP_API pp_status pp_server_poll(pp_server *s, int64_t ticket, int32_t *done, dou
 /* Blocks until every submitted request is done. */
 PP_API pp_status pp_server_drain(pp_server *s);
 
-/* Loop iterations and batched tile launches issued so far. */
+/* Loop iterations and batched tile launches issued so far, and the largest
+ * number of requests in flight at once. */
 PP_API pp_status pp_server_counters(pp_server *s, int64_t *iterations, int64_t *tile_launches, int64_t *max_in_flight);
 
-/* Finishes the queued requests, stops the loop and releases the server.
- * NULL-safe. */
+/* Bytes the weight pool holds now (buffers in use and free) and at most so
+ * far; both stay within the memory budget. */
+PP_API pp_status pp_server_pool_bytes(pp_server *s, int64_t *held, int64_t *peak);
+
+/* Finishes the queued requests, stops the loop and releases the server and
+ * its pool.  NULL-safe. */
 PP_API void pp_server_destroy(pp_server *s);
 
 /* ------------------------------------------------------------ tuning */
-/* Library-wide tuning knobs (set by the autotuner, read when a schedule is
+/* Library-wide tuning knobs (no counterpart in the paper; the shapes of the
+ * Map-stage kernels of Sec. IV-B; set by the autotuner, read when a schedule is
  * built or a kernel launched):
  *   PP_TUNE_TILE_QUBITS: index = n (8..16), value = default tile qubits k
  *                        (4..7) for circuits without PP_OPT_TILE_QUBITS;
@@ -305,7 +398,8 @@ PP_API pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value);
 PP_API pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value);
 
 /* Host-only planning introspection (no device needed): runs the DENSE
- * scheduler on a gate list and reports the number of device ops and passes
+ * scheduler (the grouping of gates into operators of Sec. III-A, here tile
+ * passes and per-wire maps, fed to the Map stage of Sec. IV-B) on a gate list and reports the number of device ops and passes
  * for tiles of k qubits (k = n: one LDS-resident pass).  compose = fold a
  * wire's single-qubit gates into one op; reorder = let gates on disjoint
  * qubits move past each other.  pass_ops (optional, capacity max_passes)
@@ -316,7 +410,8 @@ PP_API pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *
                                     int32_t compose, int32_t reorder, int64_t *n_ops, int64_t *n_passes,
                                     int32_t *pass_ops, int64_t max_passes);
 
-/* Kernel timing for measurement: while enabled (on = 1), the library's
+/* Kernel timing for measurement (the stage timings of Sec. V, taken with
+ * HIP events): while enabled (on = 1), the library's
  * kernel launches are timed with HIP events recorded on the stream they are
  * launched on.  A run of consecutive tile passes (one call's passes on one
  * stream) is bracketed by one pair of events and each of its launches is

@@ -31,6 +31,14 @@ class PPKernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class PPAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
 class PauliPropError(RuntimeError):
     def __init__(self, status, message):
         self.status = status
@@ -64,6 +72,11 @@ def load():
         "pp_evaluate_batch": (st, [P, I64, P, P]),
         "pp_evaluate_thetas": (st, [P, I64, P, I32, P, P]),
         "pp_gradient": (st, [P, P, I32, P, P]),
+        "pp_psr_gradient": (st, [P, P, P]),
+        "pp_set_allocator": (st, [ctypes.POINTER(PPAllocator)]),
+        "pp_memory_in_use": (st, [ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+        "pp_server_set_queue_limit": (st, [P, I64]),
+        "pp_server_pool_bytes": (st, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "pp_density_matrix": (st, [P, P, P]),
         "pp_circuit_set_truncation": (st, [P, ctypes.c_double, I32]),
         "pp_get_truncation": (st, [P, P, P]),
@@ -127,6 +140,13 @@ def plan_dense_info(n, op, q0, q1, param, n_params, k, compose=True, reorder=Tru
     if want_passes:
         return nops.value, npass.value, buf[: npass.value].copy()
     return nops.value, npass.value
+
+
+def memory_in_use():
+    """(bytes, blocks) of device memory the library holds."""
+    b, n = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(load().pp_memory_in_use(ctypes.byref(b), ctypes.byref(n)))
+    return b.value, n.value
 
 
 def tune_set(key, index, value):

@@ -2,7 +2,9 @@
 every step of the propagation runs in the library's HIP kernels."""
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 
 import numpy as np
 import torch
@@ -23,9 +25,78 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+# ------------------------------------------------------------ device memory
+# The library's device buffers come from torch's caching allocator (installed
+# on first use), so torch owns the device memory of the whole process.  The
+# callbacks may run on the library's own threads (serving loop, preparation
+# threads); ctypes takes the GIL for them.
+_LIVE = weakref.WeakSet()  # circuits and servers not yet closed
+_HOOK = {"struct": None, "kind": None}
+# every allocator ever installed stays alive: a block goes back to the hook
+# that made it, even after another allocator was installed
+_HOOKS_KEPT = []
+
+
+def _torch_alloc(nbytes, stream, user):
+    try:
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0)))
+    except Exception:  # out of memory: the library reports PP_ERR_NOMEM
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, user):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+def set_allocator(alloc=None, free=None):
+    """Installs the library's device allocator.  With no arguments: torch's
+    caching allocator.  Otherwise alloc(nbytes) -> device pointer (int) or
+    None, and free(ptr).  Blocks go back to the allocator that made them."""
+    lib = L.load()
+    if alloc is None:
+        a, f, kind = _torch_alloc, _torch_free, "torch"
+    else:
+        a = lambda nbytes, stream, user: alloc(int(nbytes))  # noqa: E731
+        f = lambda ptr, nbytes, stream, user: free(int(ptr))  # noqa: E731
+        kind = "custom"
+    st = L.PPAllocator(L.ALLOC_FN(a), L.FREE_FN(f), None)
+    L.check(lib.pp_set_allocator(ctypes.byref(st)))
+    _HOOK["struct"], _HOOK["kind"] = st, kind
+    _HOOKS_KEPT.append(st)
+
+
+def reset_allocator():
+    """Back to the library's default device allocator (its stream-ordered
+    pool)."""
+    L.check(L.load().pp_set_allocator(None))
+    _HOOK["kind"] = "default"
+
+
+def memory_in_use():
+    """(bytes, blocks) of device memory the library holds."""
+    return L.memory_in_use()
+
+
+@atexit.register
+def _release_at_exit():
+    # close what is still open while torch (and its allocator) is alive
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    if _HOOK["kind"] is not None and L._lib is not None:
+        L._lib.pp_set_allocator(None)
+
+
 def _require_gpu():
     if not torch.cuda.is_available():
         raise RuntimeError("pauliprop needs a HIP device (MI355X); none is visible")
+    if _HOOK["kind"] is None:
+        set_allocator()
 
 
 class Circuit:
@@ -42,6 +113,7 @@ class Circuit:
         h = ctypes.c_void_p()
         L.check(self._lib.pp_circuit_create(self.n, _DTYPES[dtype], _ENGINES[engine], ctypes.byref(h)))
         self._h = h
+        _LIVE.add(self)
         self.load_gates(op, q0, q1, param, n_params)
         self.set_observable(obs_x, obs_z, obs_c)
         if track:
@@ -67,7 +139,6 @@ class Circuit:
         q1 = np.ascontiguousarray(q1, dtype=np.int32)
         param = np.ascontiguousarray(param, dtype=np.int32)
         self._op, self._q0, self._q1, self._param = op, q0, q1, param
-        self._psr = None
         self.m = int(op.shape[0])
         L.check(self._lib.pp_circuit_load_gates(self._h, self.m, _ptr(op), _ptr(q0), _ptr(q1),
                                                 _ptr(param), int(n_params)))
@@ -78,16 +149,19 @@ class Circuit:
         z = np.ascontiguousarray(z, dtype=np.uint64)
         c = np.ascontiguousarray(c, dtype=np.float64)
         self._obs = (x, z, c)
-        self._psr = None
         L.check(self._lib.pp_circuit_set_observable(self._h, int(x.shape[0]), _ptr(x), _ptr(z), _ptr(c)))
 
     def set_theta(self, theta, stream=None):
+        if isinstance(theta, torch.Tensor):
+            theta = theta.detach()
         if isinstance(theta, torch.Tensor) and theta.is_cuda:
-            t = theta.detach().to(torch.float64).contiguous()
+            t = theta.to(torch.float64).contiguous()
             L.check(self._lib.pp_circuit_set_theta(self._h, ctypes.c_void_p(t.data_ptr()), 1,
                                                    _stream(stream)))
             self._theta_keep = t
         else:
+            if isinstance(theta, torch.Tensor):
+                theta = theta.cpu().numpy()
             a = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
             if a.size == 0:
                 a = np.zeros(1)
@@ -125,34 +199,16 @@ class Circuit:
         self._sweep_keep = keep
         return out
 
-    def psr_gradient(self, theta, stream=None):
-        """Parameter-shift gradient of <O> from 2 x (rotation gates) shifted
-        evaluations in one sweep: each rotation gate gets its own copy of its
-        parameter, shifted by +-pi/2, and the halves of the differences are
-        summed per parameter.  Uses a private circuit with one parameter per
-        rotation gate (built on first use)."""
-        import math
-        theta = np.asarray(theta.detach().cpu().numpy() if isinstance(theta, torch.Tensor) else theta,
-                           dtype=np.float64)
-        if getattr(self, "_psr", None) is None:
-            rot = np.nonzero(self._op >= 3)[0]
-            pexp = np.full(self.m, -1, np.int32)
-            pexp[rot] = np.arange(rot.size, dtype=np.int32)
-            c = Circuit(self.n, self._op, self._q0, self._q1, np.where(pexp >= 0, pexp, 0), max(rot.size, 1),
-                        self._obs[0], self._obs[1], self._obs[2], dtype=self.dtype, engine="dense")
-            self._psr = (c, rot)
-        c, rot = self._psr
-        base = theta[self._param[rot]] if rot.size else np.zeros(1)
-        R = rot.size
-        thetas = np.repeat(base[None, :], 2 * max(R, 1), axis=0)
-        for j in range(R):
-            thetas[2 * j, j] += math.pi / 2
-            thetas[2 * j + 1, j] -= math.pi / 2
-        vals = c.evaluate_thetas(thetas, stream=stream).cpu().numpy()
-        gexp = 0.5 * (vals[0::2] - vals[1::2])[:R]
-        grad = np.zeros(self.n_params)
-        np.add.at(grad, self._param[rot], gexp)
-        return torch.tensor(grad, dtype=torch.float64)
+    def psr_gradient(self, theta=None, stream=None) -> torch.Tensor:
+        """Parameter-shift gradient of <O> (a CUDA tensor of n_params
+        doubles): the library evaluates the 2 x (rotation gates) shifted
+        angle sets as one parameter sweep and sums the halved differences
+        per parameter on the device.  theta, if given, is set first."""
+        if theta is not None:
+            self.set_theta(theta, stream)
+        grad = torch.zeros(max(self.n_params, 1), dtype=torch.float64, device="cuda")
+        L.check(self._lib.pp_psr_gradient(self._h, _stream(stream), ctypes.c_void_p(grad.data_ptr())))
+        return grad[: self.n_params]
 
     def gradient(self, checkpoint_every=0, stream=None):
         ev = torch.empty((), dtype=torch.float64, device="cuda")
@@ -203,9 +259,6 @@ class Circuit:
         return s.as_dict()
 
     def close(self):
-        if getattr(self, "_psr", None) is not None:
-            self._psr[0].close()
-            self._psr = None
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.pp_circuit_destroy(self._h)
             self._h = ctypes.c_void_p()
@@ -240,6 +293,18 @@ class Server:
         L.check(self._lib.pp_server_create(int(mem_budget_bytes), int(max_active), ctypes.byref(h)))
         self._h = h
         self._keep = {}
+        _LIVE.add(self)
+
+    def set_queue_limit(self, max_queued):
+        """With max_queued > 0, submit() raises PauliPropError(PP_ERR_BUSY)
+        while that many requests wait for admission (0: no limit)."""
+        L.check(self._lib.pp_server_set_queue_limit(self._h, int(max_queued)))
+
+    def pool_bytes(self):
+        """(held, peak) bytes of the server's weight pool."""
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        L.check(self._lib.pp_server_pool_bytes(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def submit(self, circ: Circuit) -> int:
         t = ctypes.c_int64(0)
@@ -280,23 +345,31 @@ class Server:
 
 
 class _ExpvalFn(torch.autograd.Function):
+    """Forward evaluates <O> only; backward runs the adjoint gradient
+    (pp_gradient) at the angles the forward saw."""
+
     @staticmethod
     def forward(ctx, theta, circ, checkpoint_every):
         circ.set_theta(theta)
-        if theta.requires_grad:
-            ev, grad = circ.gradient(checkpoint_every)
-            ctx.save_for_backward(grad)
-        else:
-            ev = circ.evaluate()
-            ctx.save_for_backward(torch.zeros(0, dtype=torch.float64, device=ev.device))
+        ev = circ.evaluate()
+        ctx.circ = circ
+        ctx.checkpoint_every = checkpoint_every
+        ctx.save_for_backward(theta)
         return ev.clone()
 
     @staticmethod
     def backward(ctx, grad_out):
-        (grad,) = ctx.saved_tensors
-        return (grad_out * grad).to(grad.dtype), None, None
+        (theta,) = ctx.saved_tensors
+        if not ctx.needs_input_grad[0]:
+            return None, None, None
+        circ = ctx.circ
+        circ.set_theta(theta)
+        _, grad = circ.gradient(ctx.checkpoint_every)
+        g = grad_out.to(grad.device, torch.float64) * grad
+        return g.to(device=theta.device, dtype=theta.dtype), None, None
 
 
 def expval(circ: Circuit, theta: torch.Tensor, checkpoint_every: int = 0) -> torch.Tensor:
-    """<O>(theta) with an adjoint gradient behind torch.autograd."""
+    """<O>(theta) with an adjoint gradient behind torch.autograd (computed
+    in backward only)."""
     return _ExpvalFn.apply(theta, circ, checkpoint_every)

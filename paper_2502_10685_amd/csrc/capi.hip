@@ -8,15 +8,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/pauliprop.h"
@@ -40,15 +43,108 @@ pp_status fail(pp_status s, const std::string &msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));               \
     } while (0)
 
+// ------------------------------------------------------ device allocation
+// Every device buffer of the library comes from the allocator installed with
+// pp_set_allocator (for instance torch's caching allocator), or by default
+// from the stream-ordered pool: hipMallocAsync on an internal stream, which
+// is synchronized before the buffer is handed out, so the buffer can be used
+// on any stream at once.  Each block remembers the hook that made it, so a
+// later pp_set_allocator does not change where it is returned.  Before a
+// block is returned the device is synchronized: enqueued work on any stream
+// may still use it.
+struct HookBlock {
+    size_t bytes;
+    pp_allocator hook;
+    bool custom;
+    int dev;
+};
+std::mutex g_alloc_mu;
+pp_allocator g_hook{};
+bool g_hook_set = false;
+std::unordered_map<void *, HookBlock> g_blocks;
+int64_t g_block_bytes = 0;
+constexpr int kMaxDevices = 64;
+hipStream_t g_pool_stream[kMaxDevices] = {};
+
+hipError_t pool_stream(int dev, hipStream_t *s) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (!g_pool_stream[dev]) {
+        hipError_t e = hipStreamCreateWithFlags(&g_pool_stream[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            g_pool_stream[dev] = nullptr;
+            return e;
+        }
+    }
+    *s = g_pool_stream[dev];
+    return hipSuccess;
+}
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    bytes = std::max<size_t>(bytes, 1);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    pp_allocator hook;
+    bool custom;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        hook = g_hook;
+        custom = g_hook_set;
+    }
+    void *q = nullptr;
+    if (custom) {
+        q = hook.alloc(bytes, nullptr, hook.user);
+        if (!q) return hipErrorOutOfMemory;
+    } else {
+        hipStream_t s = nullptr;
+        if ((e = pool_stream(dev, &s)) != hipSuccess) return e;
+        e = hipMallocAsync(&q, bytes, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            if (q) (void)hipFreeAsync(q, s);
+            (void)hipGetLastError();
+            return e;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_blocks[q] = HookBlock{bytes, hook, custom, dev};
+        g_block_bytes += (int64_t)bytes;
+    }
+    *p = q;
+    return hipSuccess;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    HookBlock b;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        auto it = g_blocks.find(p);
+        if (it == g_blocks.end()) return;
+        b = it->second;
+        g_blocks.erase(it);
+        g_block_bytes -= (int64_t)b.bytes;
+    }
+    (void)hipDeviceSynchronize();
+    if (b.custom) {
+        b.hook.free(p, b.bytes, nullptr, b.hook.user);
+    } else {
+        hipStream_t s = nullptr;
+        if (pool_stream(b.dev, &s) == hipSuccess) (void)hipFreeAsync(p, s);
+    }
+}
+
 template <class T>
 hipError_t dalloc(T **p, size_t count) {
-    *p = nullptr;
-    return hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+    return dev_alloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
 }
 
 template <class T>
 void dfree(T *&p) {
-    if (p) (void)hipFree((void *)p);
+    dev_free((void *)p);
     p = nullptr;
 }
 
@@ -60,6 +156,35 @@ __global__ void copy_f64_kernel(const double *src, double *dst, int count) {
 __global__ void zero_u64_kernel(unsigned long long *p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0;
+}
+
+// Shifted parameter sets of the parameter-shift rule: set 2j has rotation j's
+// angle raised by pi/2, set 2j+1 lowered by pi/2, every other rotation at its
+// angle theta[rot_param[r]].
+__global__ void psr_thetas_kernel(const double *__restrict__ theta, const int32_t *__restrict__ rot_param, int R,
+                                  double *__restrict__ thetas) {
+    const long long total = 2ll * R * R;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int set = (int)(i / R), r = (int)(i % R);
+        double t = theta[rot_param[r]];
+        if (r == set / 2) t += (set & 1) ? -M_PI_2 : M_PI_2;
+        thetas[i] = t;
+    }
+}
+
+// grad[p] = sum over the rotations r of parameter p, in gate order, of
+// (f(theta_r + pi/2) - f(theta_r - pi/2)) / 2.
+__global__ void psr_combine_kernel(const double *__restrict__ vals, const int32_t *__restrict__ off,
+                                   const int32_t *__restrict__ rot, int nparams, double *__restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nparams) return;
+    double g = 0.0;
+    for (int i = off[p]; i < off[p + 1]; ++i) {
+        const int r = rot[i];
+        g += 0.5 * (vals[2 * r] - vals[2 * r + 1]);
+    }
+    grad[p] = g;
 }
 
 __global__ void compact_to_sparse_count_kernel(const unsigned long long *total, long long *count) {
@@ -224,10 +349,23 @@ struct pp_circuit {
     // density matrix: Heisenberg propagation of the inverse circuit
     pp_circuit *dm = nullptr;
     uint64_t dm_gen = ~0ull;
+    // parameter-shift gradient: the same gates with one parameter per
+    // rotation gate (rotation j reads parameter j), its shifted parameter
+    // sets and results, and the rotations of each parameter in gate order
+    pp_circuit *psr = nullptr;
+    uint64_t psr_gen = ~0ull, psr_obs_gen = ~0ull;
+    int32_t *d_psr_rot_param = nullptr;  // R: parameter of rotation j
+    int32_t *d_psr_off = nullptr;        // n_params + 1: CSR offsets into d_psr_rot
+    int32_t *d_psr_rot = nullptr;        // R: rotations grouped by parameter
+    double *d_psr_thetas = nullptr;      // 2R x R shifted parameter sets
+    double *d_psr_vals = nullptr;        // 2R results
+    int32_t psr_R = 0;
+    uint64_t obs_gen = 0;  // bumped by every pp_circuit_set_observable
 
     // schedule cache
     bool plan_valid = false;
     int plan_track = -1, plan_k = -1;
+    void *plan_coef = nullptr;  // weight array the descriptors point at
     uint64_t plan_gen = 0;  // bumped whenever device descriptors change
     pp::DensePlan dplan;
     pp::SparsePlan splan;
@@ -298,10 +436,13 @@ struct pp_circuit {
     } sw;
 
     Staging staging;
+    // recorded on the caller's stream after every theta upload, so that work
+    // the library issues on streams of its own (the serving loop) is ordered
+    // after the upload
+    hipEvent_t theta_ev = nullptr;
     pp_stats st{};
     bool evaluated = false;
     int last_track = 0;
-    hipStream_t last_stream = nullptr;
 };
 
 namespace {
@@ -384,7 +525,7 @@ void free_state_buffers(pp_circuit *c) {
 
 int64_t dense_slots(int n) { return (int64_t)1 << (2 * n); }
 
-uint64_t g_plan_gen = 0;
+std::atomic<uint64_t> g_plan_gen{0};
 
 int tile_qubits_for(const pp_circuit *c) {
     if (c->n <= kResidentMaxN &&
@@ -400,11 +541,13 @@ int tile_qubits_for(const pp_circuit *c) {
     return k;
 }
 
-pp_status ensure_state(pp_circuit *c) {
+// weights = false: DENSE circuits get no 4^n weight array of their own (the
+// serving loop runs them in buffers of its pool)
+pp_status ensure_state(pp_circuit *c, bool weights = true) {
     if (c->engine == PP_ENGINE_DENSE) {
         const int64_t slots = dense_slots(c->n);
-        if (!c->coef) {
-            hipError_t e = hipMalloc(&c->coef, (size_t)slots * c->dbytes);
+        if (weights && !c->coef) {
+            hipError_t e = dev_alloc(&c->coef, (size_t)slots * c->dbytes);
             if (e != hipSuccess) {
                 c->coef = nullptr;
                 return fail(PP_ERR_NOMEM, "dense weights: " + std::to_string(slots * c->dbytes) + " bytes");
@@ -421,7 +564,7 @@ pp_status ensure_state(pp_circuit *c) {
         c->sb.max_tiles = tiles;
         for (int i = 0; i < 6; ++i) {
             const size_t bytes = (size_t)cap2 * ((i == 2 || i == 5) ? c->dbytes : 8);
-            hipError_t e = hipMalloc(&c->sb_base[i], bytes);
+            hipError_t e = dev_alloc(&c->sb_base[i], bytes);
             if (e != hipSuccess) {
                 c->sb_base[i] = nullptr;
                 return fail(PP_ERR_NOMEM, "sparse term buffers");
@@ -454,11 +597,12 @@ pp_status upload_vec(T **dptr, const std::vector<T> &v) {
     return PP_OK;
 }
 
-pp_status ensure_plan(pp_circuit *c) {
-    pp_status r = ensure_state(c);
+pp_status ensure_plan(pp_circuit *c, bool weights = true) {
+    pp_status r = ensure_state(c, weights);
     if (r != PP_OK) return r;
     const int k = c->engine == PP_ENGINE_DENSE ? tile_qubits_for(c) : 0;
-    if (c->plan_valid && c->plan_track == c->track && c->plan_k == k) return PP_OK;
+    // the descriptors hold the weight pointer they were built with
+    if (c->plan_valid && c->plan_track == c->track && c->plan_k == k && c->plan_coef == c->coef) return PP_OK;
     free_plan_buffers(c);
     if (c->track && c->engine == PP_ENGINE_DENSE && !c->pres) HIPCHK(dalloc(&c->pres, (size_t)dense_slots(c->n)));
     if (c->engine == PP_ENGINE_SPARSE) {
@@ -525,6 +669,7 @@ pp_status ensure_plan(pp_circuit *c) {
     c->plan_valid = true;
     c->plan_track = c->track;
     c->plan_k = k;
+    c->plan_coef = c->coef;
     c->plan_gen = ++g_plan_gen;
     return PP_OK;
 }
@@ -655,6 +800,27 @@ const char *pp_version(void) { return "pauliprop 0.1 (gfx950)"; }
 
 const char *pp_last_error(void) { return g_err.c_str(); }
 
+pp_status pp_set_allocator(const pp_allocator *a) {
+    if (a && (!a->alloc || !a->free)) return fail(PP_ERR_INVALID, "allocator needs both alloc and free");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (a) {
+        g_hook = *a;
+        g_hook_set = true;
+    } else {
+        g_hook = pp_allocator{};
+        g_hook_set = false;
+    }
+    return PP_OK;
+}
+
+pp_status pp_memory_in_use(int64_t *bytes, int64_t *blocks) {
+    if (!bytes && !blocks) return fail(PP_ERR_INVALID, "null output");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (bytes) *bytes = g_block_bytes;
+    if (blocks) *blocks = (int64_t)g_blocks.size();
+    return PP_OK;
+}
+
 pp_status pp_circuit_create(int32_t n_qubits, pp_dtype dtype, pp_engine engine, pp_circuit **out) {
     if (!out) return fail(PP_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -683,9 +849,16 @@ pp_status pp_circuit_create(int32_t n_qubits, pp_dtype dtype, pp_engine engine, 
 
 void pp_circuit_destroy(pp_circuit *c) {
     if (!c) return;
-    if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+    // the streams of past evaluations may be gone (a server's, or the
+    // caller's): wait for the whole device instead
     (void)hipDeviceSynchronize();
     if (c->dm) pp_circuit_destroy(c->dm);
+    if (c->psr) pp_circuit_destroy(c->psr);
+    dfree(c->d_psr_rot_param);
+    dfree(c->d_psr_off);
+    dfree(c->d_psr_rot);
+    dfree(c->d_psr_thetas);
+    dfree(c->d_psr_vals);
     free_plan_buffers(c);
     free_state_buffers(c);
     dfree(c->d_theta);
@@ -693,6 +866,7 @@ void pp_circuit_destroy(pp_circuit *c) {
     dfree(c->d_oz);
     dfree(c->d_oc);
     c->staging.release();
+    if (c->theta_ev) (void)hipEventDestroy(c->theta_ev);
     delete c;
 }
 
@@ -800,6 +974,8 @@ pp_status pp_circuit_set_theta(pp_circuit *c, const double *theta, int32_t on_de
         pp_status r = c->staging.upload(c->d_theta, theta, sizeof(double) * np, s);
         if (r != PP_OK) return r;
     }
+    if (!c->theta_ev) HIPCHK(hipEventCreateWithFlags(&c->theta_ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(c->theta_ev, s));
     c->have_theta = true;
     return PP_OK;
 }
@@ -830,6 +1006,7 @@ pp_status pp_circuit_set_observable(pp_circuit *c, int64_t n_terms, const uint64
     c->oz.assign(z, z + n_terms);
     c->oc.assign(coeff, coeff + n_terms);
     c->have_obs = true;
+    c->obs_gen++;
     free_plan_buffers(c);  // descriptors hold the observable pointers
     return PP_OK;
 }
@@ -910,14 +1087,13 @@ pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval) {
     if (r != PP_OK) return r;
     c->evaluated = true;
     c->last_track = c->track;
-    c->last_stream = s;
     return PP_OK;
 }
 
 pp_status pp_get_stats(pp_circuit *c, pp_stats *out) {
     if (!c || !out) return fail(PP_ERR_INVALID, "null argument");
     if (c->evaluated) {
-        HIPCHK(hipStreamSynchronize(c->last_stream));
+        HIPCHK(hipDeviceSynchronize());  // its stream may no longer exist
         if (c->engine == PP_ENGINE_SPARSE) {
             long long cnt[2] = {0, 0};
             unsigned long long upd = 0;
@@ -970,13 +1146,12 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
         tmp.cap2 = slots;
         tmp.max_tiles = tiles;
         bool ok = true;
-        for (int i = 0; i < 6 && ok; ++i) ok = hipMalloc(&tmp_base[i], (size_t)slots * 8) == hipSuccess;
-        ok = ok && hipMalloc((void **)&tmp.count, 8 * sizeof(long long)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&tmp.scan, 256 * sizeof(long long)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&tmp.updates, sizeof(unsigned long long)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&tmp.hist, (size_t)256 * tiles * sizeof(unsigned)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&tmp.tile_flags, (size_t)std::max<int64_t>(tiles, slots / 4096 + 1) * sizeof(int)) ==
-                       hipSuccess;
+        for (int i = 0; i < 6 && ok; ++i) ok = dev_alloc(&tmp_base[i], (size_t)slots * 8) == hipSuccess;
+        ok = ok && dalloc(&tmp.count, 8) == hipSuccess;
+        ok = ok && dalloc(&tmp.scan, 256) == hipSuccess;
+        ok = ok && dalloc(&tmp.updates, 1) == hipSuccess;
+        ok = ok && dalloc(&tmp.hist, (size_t)256 * tiles) == hipSuccess;
+        ok = ok && dalloc(&tmp.tile_flags, (size_t)std::max<int64_t>(tiles, slots / 4096 + 1)) == hipSuccess;
         unsigned long long *total = c->d_counters + 2;
         if (ok) {
             tmp.x = (uint64_t *)tmp_base[0];
@@ -1086,7 +1261,6 @@ pp_status pp_density_matrix(pp_circuit *c, void *stream, double *d_rho) {
     if ((r = ensure_state(a)) != PP_OK) return r;
     if ((r = pp_evaluate(a, stream, a->d_result)) != PP_OK) return r;
     HIPCHK(pp::launch_density_decode(a->coef, a->n, a->dbytes, d_rho, s));
-    c->last_stream = s;
     return PP_OK;
 }
 
@@ -1141,6 +1315,15 @@ BatchCache g_batch;
 extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, void *stream, double *d_expvals) {
     if (count < 0 || (count > 0 && (!cs || !d_expvals))) return fail(PP_ERR_INVALID, "bad batch arguments");
     if (count == 0) return PP_OK;
+    {
+        // one circuit twice would scatter its observable into its one weight
+        // array twice and put two workgroups on the same tiles
+        std::unordered_set<const pp_circuit *> seen;
+        seen.reserve((size_t)count);
+        for (int64_t i = 0; i < count; ++i)
+            if (cs[i] && !seen.insert(cs[i]).second)
+                return fail(PP_ERR_INVALID, "circuit " + std::to_string(i) + " appears twice in the batch");
+    }
     hipStream_t s = (hipStream_t)stream;
     pp_status r;
     int dbytes = -1;
@@ -1268,7 +1451,8 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         if (blob.size() > B.dcap) {
             if (B.dbuf) HIPCHK(hipStreamSynchronize(s));
             dfree(B.dbuf);
-            HIPCHK(hipMalloc(&B.dbuf, blob.size()));
+            B.dcap = 0;
+            HIPCHK(dev_alloc(&B.dbuf, blob.size()));
             B.dcap = blob.size();
         }
         if (!blob.empty()) {
@@ -1329,7 +1513,6 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
     for (int64_t i = 0; i < count; ++i) {
         cs[i]->evaluated = true;
         cs[i]->last_track = cs[i]->track;
-        cs[i]->last_stream = s;
     }
     return PP_OK;
 }
@@ -1470,9 +1653,9 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
         HIPCHK(hipStreamSynchronize(s));
         if (W.gen != c->plan_gen || count > W.cap) free_sweep(c);
         const int64_t cap = count;
-        hipError_t e = hipMalloc((void **)&W.thetas, sizeof(double) * np * cap);
-        if (e == hipSuccess) e = hipMalloc((void **)&W.maps, sizeof(double) * 9 * nm * cap);
-        if (e == hipSuccess && !P.resident) e = hipMalloc(&W.coef, (size_t)slots * c->dbytes * cap);
+        hipError_t e = dalloc(&W.thetas, (size_t)(np * cap));
+        if (e == hipSuccess) e = dalloc(&W.maps, (size_t)(9 * nm * cap));
+        if (e == hipSuccess && !P.resident) e = dev_alloc(&W.coef, (size_t)slots * c->dbytes * cap);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             free_sweep(c);
@@ -1528,7 +1711,8 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
         if (blob.size() > W.dcap) {
             HIPCHK(hipStreamSynchronize(s));
             dfree(W.dbuf);
-            HIPCHK(hipMalloc(&W.dbuf, blob.size()));
+            W.dcap = 0;
+            HIPCHK(dev_alloc(&W.dbuf, blob.size()));
             W.dcap = blob.size();
         }
         r = W.staging.upload(W.dbuf, blob.data(), blob.size(), s);
@@ -1574,7 +1758,6 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
         ProfScope ps(PC_READOUT, s);
         HIPCHK(pp::launch_dense_readout(W.coef, c->n, c->dbytes, d_expvals, s, (int)count));
     }
-    c->last_stream = s;
     return PP_OK;
 }
 
@@ -1628,7 +1811,83 @@ extern "C" pp_status pp_gradient(pp_circuit *c, void *stream, int32_t checkpoint
     }
     fill_plan_stats(c);
     c->evaluated = false;  // the dense weights now hold the forward-swept set
-    c->last_stream = s;
+    return PP_OK;
+}
+
+// Parameter-shift gradient (the rule of Sec. I: a rotation's derivative is
+// half the difference of two evaluations at its angle +- pi/2), as one
+// parameter sweep over 2R shifted sets of a private circuit in which every
+// rotation gate has a parameter of its own.
+extern "C" pp_status pp_psr_gradient(pp_circuit *c, void *stream, double *d_grad) {
+    pp_status r = check_ready(c);
+    if (r != PP_OK) return r;
+    if (c->g.n_params > 0 && !d_grad) return fail(PP_ERR_INVALID, "d_grad is NULL");
+    if (c->engine != PP_ENGINE_DENSE || c->track)
+        return fail(PP_ERR_STATE, "pp_psr_gradient runs on the DENSE engine without term tracking");
+    hipStream_t s = (hipStream_t)stream;
+    const int np = c->g.n_params;
+    int R = 0;
+    for (int64_t g = 0; g < c->g.m; ++g) R += c->g.op[(size_t)g] >= PP_RX;
+    if ((int64_t)2 * R * R > ((int64_t)1 << 27))
+        return fail(PP_ERR_CAPACITY, "parameter-shift sweep over " + std::to_string(R) + " rotations is too large");
+    if (np == 0) return PP_OK;
+    if (R == 0) {
+        HIPCHK(hipMemsetAsync(d_grad, 0, sizeof(double) * np, s));
+        return PP_OK;
+    }
+    if (!c->psr || c->psr_gen != c->gates_gen || c->psr_obs_gen != c->obs_gen) {
+        if (c->psr) pp_circuit_destroy(c->psr);
+        c->psr = nullptr;
+        dfree(c->d_psr_rot_param);
+        dfree(c->d_psr_off);
+        dfree(c->d_psr_rot);
+        dfree(c->d_psr_thetas);
+        dfree(c->d_psr_vals);
+        const int64_t m = c->g.m;
+        std::vector<int32_t> pexp((size_t)m, 0), rot_param;
+        std::vector<std::vector<int32_t>> by_param((size_t)np);
+        for (int64_t g = 0; g < m; ++g)
+            if (c->g.op[(size_t)g] >= PP_RX) {
+                const int32_t j = (int32_t)rot_param.size();
+                pexp[(size_t)g] = j;
+                rot_param.push_back(c->g.param[(size_t)g]);
+                by_param[(size_t)c->g.param[(size_t)g]].push_back(j);
+            }
+        std::vector<int32_t> off(1, 0), rots;
+        for (auto &v : by_param) {
+            rots.insert(rots.end(), v.begin(), v.end());
+            off.push_back((int32_t)rots.size());
+        }
+        pp_circuit *a = nullptr;
+        if ((r = pp_circuit_create(c->n, c->dtype, PP_ENGINE_DENSE, &a)) != PP_OK) return r;
+        r = pp_circuit_load_gates(a, m, c->g.op.data(), c->g.q0.data(), c->g.q1.data(), pexp.data(), R);
+        if (r == PP_OK) r = pp_circuit_set_observable(a, (int64_t)c->ox.size(), c->ox.data(), c->oz.data(), c->oc.data());
+        if (r == PP_OK && c->tile_opt) r = pp_circuit_set_option(a, PP_OPT_TILE_QUBITS, c->tile_opt);
+        if (r == PP_OK) r = upload_vec(&c->d_psr_rot_param, rot_param);
+        if (r == PP_OK) r = upload_vec(&c->d_psr_off, off);
+        if (r == PP_OK) r = upload_vec(&c->d_psr_rot, rots);
+        if (r == PP_OK && dalloc(&c->d_psr_thetas, (size_t)2 * R * R) != hipSuccess)
+            r = fail(PP_ERR_NOMEM, "parameter-shift sets");
+        if (r == PP_OK && dalloc(&c->d_psr_vals, (size_t)2 * R) != hipSuccess)
+            r = fail(PP_ERR_NOMEM, "parameter-shift results");
+        if (r != PP_OK) {
+            pp_circuit_destroy(a);
+            return r;
+        }
+        c->psr = a;
+        c->psr_gen = c->gates_gen;
+        c->psr_obs_gen = c->obs_gen;
+        c->psr_R = R;
+    }
+    const long long total = 2ll * R * R;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(psr_thetas_kernel, dim3(blocks), dim3(256), 0, s, c->d_theta, c->d_psr_rot_param, R,
+                       c->d_psr_thetas);
+    HIPCHK(hipGetLastError());
+    if ((r = pp_evaluate_thetas(c->psr, 2 * R, c->d_psr_thetas, 1, stream, c->d_psr_vals)) != PP_OK) return r;
+    hipLaunchKernelGGL(psr_combine_kernel, dim3((np + 255) / 256), dim3(256), 0, s, c->d_psr_vals, c->d_psr_off,
+                       c->d_psr_rot, np, d_grad);
+    HIPCHK(hipGetLastError());
     return PP_OK;
 }
 
@@ -1743,16 +2002,19 @@ int64_t footprint_bytes(const pp_circuit *c) {
     return 2 * cap * (16 + 2 * (int64_t)c->dbytes);
 }
 
+enum ReqState { RQ_PREP = 0, RQ_QUEUED, RQ_ACTIVE, RQ_FINISHING, RQ_DONE };
+
 struct ServedReq {
     int64_t ticket = 0;
     pp_circuit *c = nullptr;
-    int state = 0;  // 0 queued, 1 admitted, 2 finishing, 3 done
-    bool prepared = false;
-    int64_t foot = 0;
+    std::atomic<int> state{RQ_PREP};  // written by the serving thread, read by pp_server_poll
+    bool resident = false;  // runs whole in one LDS-resident launch
+    bool pooled = false;    // tiled DENSE: weights in a buffer of the server's pool
+    void *buf = nullptr;    // the pool buffer while active
+    int64_t foot = 0;       // bytes counted against the budget while active
     double t_submit = 0, t_done = 0;
     size_t pass = 0;
     int slot = -1;
-    bool resident = false;  // runs whole in one LDS-resident launch
     hipEvent_t ev = nullptr;
     double result = 0;
     pp_status status = PP_OK;
@@ -1763,23 +2025,35 @@ constexpr int kRing = 4;
 // their own beside the tile passes (kernels of one stream run in order, so a
 // single side stream would serialize one-workgroup launches)
 constexpr int kSideLanes = 3;
+// host threads that plan admitted-to-be requests (planning a 60k-gate
+// circuit takes tens of milliseconds of host time)
+constexpr int kPrepThreads = 4;
 
 }  // namespace
 
 struct pp_server {
     std::mutex mu;
-    std::condition_variable cv, done_cv;
+    std::condition_variable cv, done_cv, prep_cv;
     std::thread th;
+    std::vector<std::thread> preps;
     bool stop = false;
-    std::deque<ServedReq *> queue;
+    std::deque<ServedReq *> prep_queue;  // submitted, waiting for a preparation thread
+    int preparing = 0;                   // being prepared
+    std::deque<ServedReq *> queue;       // prepared, waiting for admission (ticket order)
     std::vector<ServedReq *> active;
     std::unordered_map<int64_t, ServedReq *> reqs;
+    std::unordered_set<const pp_circuit *> live;  // circuits submitted and not done
     int64_t next_ticket = 1;
     int64_t budget = 0, used = 0;
+    int64_t max_queued = 0;  // 0: no limit
     int max_active = 0;
     hipStream_t main = nullptr, side = nullptr;
     double *d_results = nullptr, *h_results = nullptr;
     std::vector<int> free_slots;
+    // weight buffers of tiled requests: returned at completion and reused;
+    // held (in use + free) never exceeds the budget
+    std::multimap<size_t, void *> pool_free;
+    int64_t pool_held = 0, pool_peak = 0;
     struct Ring {
         void *d = nullptr, *h = nullptr;
         size_t cap = 0;
@@ -1806,11 +2080,12 @@ pp_status ring_upload(pp_server *S, const std::vector<unsigned char> &blob, void
     S->ring_i = (S->ring_i + 1) % kRing;
     if (R.used) HIPCHK(hipEventSynchronize(R.ev));  // bounds how far the host runs ahead
     if (blob.size() > R.cap) {
-        if (R.d) (void)hipFree(R.d);
+        dev_free(R.d);
         if (R.h) (void)hipHostFree(R.h);
         R.d = R.h = nullptr;
+        R.cap = 0;
         const size_t cap = std::max<size_t>(blob.size() * 2, 1 << 16);
-        HIPCHK(hipMalloc(&R.d, cap));
+        HIPCHK(dev_alloc(&R.d, cap));
         HIPCHK(hipHostMalloc(&R.h, cap, hipHostMallocDefault));
         R.cap = cap;
     }
@@ -1826,33 +2101,79 @@ void ring_mark(pp_server *S) {
     if (hipEventRecord(R.ev, S->main) == hipSuccess) R.used = true;
 }
 
+// A weight buffer of `bytes` from the pool: a free one of that size, else a
+// new one, after returning free buffers of other sizes while the pool would
+// exceed the budget.  Admission keeps the active footprints within the
+// budget, so the free buffers always cover the difference.
+pp_status pool_take(pp_server *S, size_t bytes, void **out) {
+    auto it = S->pool_free.find(bytes);
+    if (it != S->pool_free.end()) {
+        *out = it->second;
+        S->pool_free.erase(it);
+        return PP_OK;
+    }
+    while (S->pool_held + (int64_t)bytes > S->budget && !S->pool_free.empty()) {
+        auto big = std::prev(S->pool_free.end());
+        dev_free(big->second);
+        S->pool_held -= (int64_t)big->first;
+        S->pool_free.erase(big);
+    }
+    void *p = nullptr;
+    HIPCHK(dev_alloc(&p, bytes));
+    S->pool_held += (int64_t)bytes;
+    S->pool_peak = std::max(S->pool_peak, S->pool_held);
+    *out = p;
+    return PP_OK;
+}
+
 pp_status finish_async(pp_server *S, ServedReq *r, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(S->h_results + r->slot, S->d_results + r->slot, sizeof(double), hipMemcpyDeviceToHost, st));
     if (!r->ev) HIPCHK(hipEventCreateWithFlags(&r->ev, hipEventDisableTiming));
     HIPCHK(hipEventRecord(r->ev, st));
-    r->state = 2;
+    r->state = RQ_FINISHING;
     return PP_OK;
 }
 
-// Prepares an admitted request and starts what runs whole.
-pp_status start_request(pp_server *S, ServedReq *r) {
+// Orders the work about to be issued on `st` after the request's theta upload
+// (made by the caller on a stream of its own before pp_server_submit).
+pp_status after_theta(const pp_circuit *c, hipStream_t st) {
+    if (c->theta_ev) HIPCHK(hipStreamWaitEvent(st, c->theta_ev, 0));
+    return PP_OK;
+}
+
+// Preparation, on a preparation thread: the schedule is built and uploaded
+// (the circuit's own 4^n weights are not allocated for DENSE circuits
+// without term tracking: tiled ones run in pool buffers, LDS-resident ones
+// need none).
+pp_status prepare_request(ServedReq *r) {
     pp_circuit *c = r->c;
-    pp_status st = ensure_plan(c);
+    const bool dense_fast = c->engine == PP_ENGINE_DENSE && !c->track;
+    pp_status st = ensure_plan(c, !dense_fast);
     if (st != PP_OK) return st;
     fill_plan_stats(c);
-    r->prepared = true;
+    r->resident = dense_fast && c->dplan.resident;
+    r->pooled = dense_fast && !c->dplan.resident;
+    r->foot = r->resident ? 0 : footprint_bytes(c);
+    return PP_OK;
+}
+
+// Starts an admitted request: the whole evaluation for requests outside the
+// batched paths; maps and start weights for tiled ones.
+pp_status start_request(pp_server *S, ServedReq *r) {
+    pp_circuit *c = r->c;
     double *out = S->d_results + r->slot;
-    if (c->engine == PP_ENGINE_DENSE && !c->track && c->dplan.resident) {
-        r->resident = true;  // launched with the other pending resident requests
-        return PP_OK;
-    }
-    if (c->engine != PP_ENGINE_DENSE || c->track) {
-        st = pp_evaluate(c, S->side, out);
+    if (r->resident) return PP_OK;  // launched with the other pending resident requests
+    if (!r->pooled) {
+        pp_status st = after_theta(c, S->side);
+        if (st == PP_OK) st = pp_evaluate(c, S->side, out);
         if (st != PP_OK) return st;
         return finish_async(S, r, S->side);
     }
+    pp_status st = pool_take(S, (size_t)r->foot, &r->buf);
+    if (st != PP_OK) return st;
+    if ((st = after_theta(c, S->main)) != PP_OK) return st;
     if (c->dplan.nmaps() > 0) HIPCHK(pp::launch_compose(c->d_comp, 1, S->main, c->dplan.nmaps()));
-    HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(),
+    HIPCHK(pp::launch_dense_init(r->buf, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(),
                                  S->main));
     r->pass = 0;
     return PP_OK;
@@ -1860,7 +2181,7 @@ pp_status start_request(pp_server *S, ServedReq *r) {
 
 // Launches every pending resident request on an idle side lane: the maps of
 // all of them in one compose launch, then one resident launch per (dtype, n)
-// with one workgroup per request.  Returns false when every lane is busy.
+// with one workgroup per request.  Does nothing while every lane is busy.
 pp_status launch_resident_batch(pp_server *S, bool *launched) {
     *launched = false;
     pp_server::SideLane *Ln = nullptr;
@@ -1893,14 +2214,18 @@ pp_status launch_resident_batch(pp_server *S, bool *launched) {
     const size_t roff = (cbytes + 255) & ~(size_t)255;
     const size_t bytes = roff + rd.size() * sizeof(pp::ResidentDesc);
     if (bytes > Ln->cap) {  // the lane is idle: its buffers are free
-        if (Ln->d) (void)hipFree(Ln->d);
+        dev_free(Ln->d);
         if (Ln->h) (void)hipHostFree(Ln->h);
         Ln->d = Ln->h = nullptr;
         Ln->cap = 0;
         const size_t cap = std::max<size_t>(2 * bytes, 1 << 16);
-        HIPCHK(hipMalloc(&Ln->d, cap));
+        HIPCHK(dev_alloc(&Ln->d, cap));
         HIPCHK(hipHostMalloc(&Ln->h, cap, hipHostMallocDefault));
         Ln->cap = cap;
+    }
+    for (ServedReq *r : P) {
+        pp_status st = after_theta(r->c, Ln->st);
+        if (st != PP_OK) return st;
     }
     if (!comp.empty()) std::memcpy(Ln->h, comp.data(), cbytes);
     std::memcpy((unsigned char *)Ln->h + roff, rd.data(), rd.size() * sizeof(pp::ResidentDesc));
@@ -1927,14 +2252,56 @@ pp_status launch_resident_batch(pp_server *S, bool *launched) {
     return PP_OK;
 }
 
+// Marks a request done (caller holds S->mu).  A tiled request's pool buffer
+// goes back to the pool: its last use (the readout) came before the event
+// that completed it, and a failed request has nothing left in flight on it
+// once the server stream it used has been synchronized by the caller.
 void complete(pp_server *S, ServedReq *r, pp_status st) {
     r->status = st;
     r->t_done = now_s();
     if (st == PP_OK) r->result = S->h_results[r->slot];
-    r->state = 3;
-    r->c->evaluated = true;
-    r->c->last_track = r->c->track;
-    r->c->last_stream = r->c->engine == PP_ENGINE_DENSE && !r->c->track && !r->c->dplan.resident ? S->main : S->side;
+    r->state = RQ_DONE;
+    pp_circuit *c = r->c;
+    if (r->buf) {
+        S->pool_free.emplace((size_t)r->foot, r->buf);
+        r->buf = nullptr;
+    }
+    // a pooled run keeps no final weights with the circuit
+    c->evaluated = !r->pooled && !r->resident && st == PP_OK;
+    c->last_track = c->track;
+    S->live.erase(c);
+}
+
+bool server_idle(const pp_server *S) {
+    return S->prep_queue.empty() && S->preparing == 0 && S->queue.empty() && S->active.empty();
+}
+
+void prep_loop(pp_server *S) {
+    (void)hipSetDevice(S->dev);
+    for (;;) {
+        ServedReq *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->prep_cv.wait(lk, [&] { return S->stop || !S->prep_queue.empty(); });
+            if (S->prep_queue.empty()) return;  // stopping, nothing left
+            r = S->prep_queue.front();
+            S->prep_queue.pop_front();
+            S->preparing++;
+        }
+        const pp_status st = prepare_request(r);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->preparing--;
+        if (st != PP_OK) {
+            complete(S, r, st);
+            S->done_cv.notify_all();
+        } else {
+            r->state = RQ_QUEUED;
+            auto pos = std::upper_bound(S->queue.begin(), S->queue.end(), r,
+                                        [](const ServedReq *a, const ServedReq *b) { return a->ticket < b->ticket; });
+            S->queue.insert(pos, r);
+        }
+        S->cv.notify_all();
+    }
 }
 
 void server_loop(pp_server *S) {
@@ -1944,7 +2311,8 @@ void server_loop(pp_server *S) {
         fresh.clear();
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            if (S->stop && S->queue.empty() && S->active.empty()) break;
+            if (S->stop && server_idle(S)) break;
+            // admission in ticket order among the prepared requests
             while (!S->queue.empty() && (int)S->active.size() < S->max_active && !S->free_slots.empty()) {
                 ServedReq *r = S->queue.front();
                 if (S->used + r->foot > S->budget && !S->active.empty()) break;  // wait for memory
@@ -1952,13 +2320,17 @@ void server_loop(pp_server *S) {
                 S->used += r->foot;
                 r->slot = S->free_slots.back();
                 S->free_slots.pop_back();
-                r->state = 1;
+                r->state = RQ_ACTIVE;
                 S->active.push_back(r);
                 fresh.push_back(r);
             }
             S->max_in_flight = std::max<int64_t>(S->max_in_flight, (int64_t)S->active.size());
             if (S->active.empty()) {
-                S->cv.wait_for(lk, std::chrono::milliseconds(2));
+                // nothing in flight: sleep until a prepared request is queued
+                // (a preparation thread notifies) or the server stops
+                S->cv.wait(lk, [&] {
+                    return !S->queue.empty() || (S->stop && S->prep_queue.empty() && S->preparing == 0);
+                });
                 continue;
             }
         }
@@ -1966,6 +2338,7 @@ void server_loop(pp_server *S) {
             pp_status st = start_request(S, r);
             if (st != PP_OK) {
                 (void)hipStreamSynchronize(S->main);
+                (void)hipStreamSynchronize(S->side);
                 std::lock_guard<std::mutex> lk(S->mu);
                 complete(S, r, st);
             } else if (r->resident) {
@@ -1977,83 +2350,88 @@ void server_loop(pp_server *S) {
             std::vector<ServedReq *> batch = S->res_pending;
             pp_status st = launch_resident_batch(S, &res_launched);
             if (st != PP_OK) {
+                for (auto &Ln : S->lane) (void)hipStreamSynchronize(Ln.st);
                 std::lock_guard<std::mutex> lk(S->mu);
                 for (ServedReq *r : batch)
-                    if (r->state == 1) complete(S, r, st);
+                    if (r->state == RQ_ACTIVE) complete(S, r, st);
                 S->res_pending.clear();
             }
         }
         // one iteration: the next pass of every active tiled request, one
-        // launch per tile size
+        // launch per (tile size, weight type)
         std::vector<ServedReq *> tiled;
         for (ServedReq *r : S->active)
-            if (r->state == 1 && r->prepared && !r->resident) tiled.push_back(r);
+            if (r->state == RQ_ACTIVE && r->pooled) tiled.push_back(r);
         bool launched = false;
-        for (int k = 4; k <= 7 && !tiled.empty(); ++k) {
-            std::vector<ServedReq *> grp;
-            for (ServedReq *r : tiled)
-                if (r->c->dplan.k == k && r->pass < r->c->h_pass.size()) grp.push_back(r);
-            if (grp.empty()) continue;
-            std::stable_sort(grp.begin(), grp.end(), [](ServedReq *a, ServedReq *b) { return a->c->n > b->c->n; });
-            size_t i0 = 0;
-            while (i0 < grp.size()) {
-                std::vector<pp::TilePassDesc> td;
-                pp::TileGroups tg{};
-                int run = 0, last_n = -1;
-                size_t i = i0;
-                for (; i < grp.size(); ++i) {
-                    pp::TilePassDesc d = grp[i]->c->h_pass[grp[i]->pass];
-                    if (d.n != last_n) {
-                        if (tg.ngroups == pp::kMaxTileGroups) break;
-                        tg.first_block[tg.ngroups] = run;
-                        tg.first_desc[tg.ngroups] = (int32_t)td.size();
-                        tg.shift[tg.ngroups] = 2 * (d.n - k);
-                        tg.ngroups++;
-                        last_n = d.n;
+        for (int db : {8, 4})
+            for (int k = 4; k <= 7 && !tiled.empty(); ++k) {
+                std::vector<ServedReq *> grp;
+                for (ServedReq *r : tiled)
+                    if (r->c->dplan.k == k && r->c->dbytes == db && r->pass < r->c->h_pass.size()) grp.push_back(r);
+                if (grp.empty()) continue;
+                std::stable_sort(grp.begin(), grp.end(), [](ServedReq *a, ServedReq *b) { return a->c->n > b->c->n; });
+                size_t i0 = 0;
+                while (i0 < grp.size()) {
+                    std::vector<pp::TilePassDesc> td;
+                    pp::TileGroups tg{};
+                    int run = 0, last_n = -1;
+                    size_t i = i0;
+                    for (; i < grp.size(); ++i) {
+                        pp::TilePassDesc d = grp[i]->c->h_pass[grp[i]->pass];
+                        d.coef = grp[i]->buf;
+                        if (d.n != last_n) {
+                            if (tg.ngroups == pp::kMaxTileGroups) break;
+                            tg.first_block[tg.ngroups] = run;
+                            tg.first_desc[tg.ngroups] = (int32_t)td.size();
+                            tg.shift[tg.ngroups] = 2 * (d.n - k);
+                            tg.ngroups++;
+                            last_n = d.n;
+                        }
+                        d.tile_begin = run;
+                        run += d.ntiles;
+                        td.push_back(d);
                     }
-                    d.tile_begin = run;
-                    run += d.ntiles;
-                    td.push_back(d);
-                }
-                tg.first_block[tg.ngroups] = run;
-                std::vector<unsigned char> blob(td.size() * sizeof(pp::TilePassDesc));
-                std::memcpy(blob.data(), td.data(), blob.size());
-                void *dd = nullptr;
-                pp_status st = ring_upload(S, blob, &dd);
-                if (st == PP_OK) {
-                    hipError_t e = pp::launch_tile_pass((const pp::TilePassDesc *)dd, tg, k, grp[i0]->c->dbytes,
-                                                        false, S->main);
-                    if (e != hipSuccess) st = fail(PP_ERR_DEVICE, hipGetErrorString(e));
-                }
-                ring_mark(S);
-                for (size_t j = i0; j < i; ++j) {
-                    ServedReq *r = grp[j];
-                    if (st != PP_OK) {
-                        std::lock_guard<std::mutex> lk(S->mu);
-                        complete(S, r, st);
-                        continue;
+                    tg.first_block[tg.ngroups] = run;
+                    std::vector<unsigned char> blob(td.size() * sizeof(pp::TilePassDesc));
+                    std::memcpy(blob.data(), td.data(), blob.size());
+                    void *dd = nullptr;
+                    pp_status st = ring_upload(S, blob, &dd);
+                    if (st == PP_OK) {
+                        hipError_t e = pp::launch_tile_pass((const pp::TilePassDesc *)dd, tg, k, db, false, S->main);
+                        if (e != hipSuccess) st = fail(PP_ERR_DEVICE, hipGetErrorString(e));
                     }
-                    if (++r->pass == r->c->h_pass.size()) {
-                        pp_circuit *c = r->c;
-                        if (pp::launch_dense_readout(c->coef, c->n, c->dbytes, S->d_results + r->slot, S->main) !=
-                                hipSuccess ||
-                            finish_async(S, r, S->main) != PP_OK) {
+                    ring_mark(S);
+                    for (size_t j = i0; j < i; ++j) {
+                        ServedReq *r = grp[j];
+                        if (st != PP_OK) {
+                            (void)hipStreamSynchronize(S->main);
                             std::lock_guard<std::mutex> lk(S->mu);
-                            complete(S, r, PP_ERR_DEVICE);
+                            complete(S, r, st);
+                            continue;
+                        }
+                        if (++r->pass == r->c->h_pass.size()) {
+                            pp_circuit *c = r->c;
+                            if (pp::launch_dense_readout(r->buf, c->n, c->dbytes, S->d_results + r->slot, S->main) !=
+                                    hipSuccess ||
+                                finish_async(S, r, S->main) != PP_OK) {
+                                (void)hipStreamSynchronize(S->main);
+                                std::lock_guard<std::mutex> lk(S->mu);
+                                complete(S, r, PP_ERR_DEVICE);
+                            }
                         }
                     }
+                    S->tile_launches++;
+                    launched = true;
+                    i0 = i;
                 }
-                S->tile_launches++;
-                launched = true;
-                i0 = i;
             }
-        }
         // tiled requests with no passes at all (empty circuits)
         for (ServedReq *r : tiled)
-            if (r->state == 1 && r->c->h_pass.empty()) {
+            if (r->state == RQ_ACTIVE && r->c->h_pass.empty()) {
                 pp_circuit *c = r->c;
-                if (pp::launch_dense_readout(c->coef, c->n, c->dbytes, S->d_results + r->slot, S->main) != hipSuccess ||
+                if (pp::launch_dense_readout(r->buf, c->n, c->dbytes, S->d_results + r->slot, S->main) != hipSuccess ||
                     finish_async(S, r, S->main) != PP_OK) {
+                    (void)hipStreamSynchronize(S->main);
                     std::lock_guard<std::mutex> lk(S->mu);
                     complete(S, r, PP_ERR_DEVICE);
                 }
@@ -2063,11 +2441,11 @@ void server_loop(pp_server *S) {
         {
             std::lock_guard<std::mutex> lk(S->mu);
             for (ServedReq *r : S->active)
-                if (r->state == 2 && hipEventQuery(r->ev) == hipSuccess) complete(S, r, PP_OK);
+                if (r->state == RQ_FINISHING && hipEventQuery(r->ev) == hipSuccess) complete(S, r, PP_OK);
             bool any = false;
             for (size_t i = 0; i < S->active.size();) {
                 ServedReq *r = S->active[i];
-                if (r->state == 3) {
+                if (r->state == RQ_DONE) {
                     S->used -= r->foot;
                     S->free_slots.push_back(r->slot);
                     S->active[i] = S->active.back();
@@ -2099,20 +2477,30 @@ extern "C" pp_status pp_server_create(int64_t mem_budget_bytes, int32_t max_acti
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking);
     for (auto &Ln : S->lane)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&Ln.st, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc((void **)&S->d_results, sizeof(double) * max_active);
+    if (e == hipSuccess) e = dalloc(&S->d_results, (size_t)max_active);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_results, sizeof(double) * max_active, hipHostMallocDefault);
     if (e != hipSuccess) {
         if (S->main) (void)hipStreamDestroy(S->main);
         if (S->side) (void)hipStreamDestroy(S->side);
         for (auto &Ln : S->lane)
             if (Ln.st) (void)hipStreamDestroy(Ln.st);
-        if (S->d_results) (void)hipFree(S->d_results);
+        dfree(S->d_results);
         delete S;
-        return fail(PP_ERR_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
+        return fail(e == hipErrorOutOfMemory ? PP_ERR_NOMEM : PP_ERR_DEVICE,
+                    std::string("server setup: ") + hipGetErrorString(e));
     }
     for (int i = max_active - 1; i >= 0; --i) S->free_slots.push_back(i);
     S->th = std::thread(server_loop, S);
+    for (int i = 0; i < kPrepThreads; ++i) S->preps.emplace_back(prep_loop, S);
     *out = S;
+    return PP_OK;
+}
+
+extern "C" pp_status pp_server_set_queue_limit(pp_server *S, int64_t max_queued) {
+    if (!S) return fail(PP_ERR_INVALID, "null server");
+    if (max_queued < 0) return fail(PP_ERR_INVALID, "max_queued must be >= 0");
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->max_queued = max_queued;
     return PP_OK;
 }
 
@@ -2120,25 +2508,24 @@ extern "C" pp_status pp_server_submit(pp_server *S, pp_circuit *c, int64_t *tick
     if (!S || !c || !ticket) return fail(PP_ERR_INVALID, "null argument");
     pp_status r = check_ready(c);
     if (r != PP_OK) return r;
+    const int64_t foot = footprint_bytes(c);
+    if (foot > S->budget) return fail(PP_ERR_CAPACITY, "request larger than the server memory budget");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(PP_ERR_STATE, "server is shutting down");
+    if (S->live.count(c)) return fail(PP_ERR_INVALID, "circuit already submitted and not done");
+    if (S->max_queued > 0 && (int64_t)(S->prep_queue.size() + S->preparing + S->queue.size()) >= S->max_queued)
+        return fail(PP_ERR_BUSY, "server queue is full");
     ServedReq *q = new (std::nothrow) ServedReq();
     if (!q) return fail(PP_ERR_NOMEM, "host allocation");
     q->c = c;
-    q->foot = footprint_bytes(c);
-    if (q->foot > S->budget) {
-        delete q;
-        return fail(PP_ERR_CAPACITY, "request larger than the server memory budget");
-    }
-    std::lock_guard<std::mutex> lk(S->mu);
-    if (S->stop) {
-        delete q;
-        return fail(PP_ERR_STATE, "server is shutting down");
-    }
+    q->foot = foot;
     q->ticket = S->next_ticket++;
     q->t_submit = now_s();
-    S->queue.push_back(q);
+    S->live.insert(c);
+    S->prep_queue.push_back(q);
     S->reqs[q->ticket] = q;
     *ticket = q->ticket;
-    S->cv.notify_one();
+    S->prep_cv.notify_one();
     return PP_OK;
 }
 
@@ -2148,8 +2535,8 @@ extern "C" pp_status pp_server_poll(pp_server *S, int64_t ticket, int32_t *done,
     auto it = S->reqs.find(ticket);
     if (it == S->reqs.end()) return fail(PP_ERR_INVALID, "unknown ticket");
     ServedReq *q = it->second;
-    *done = q->state == 3;
-    if (q->state == 3) {
+    *done = q->state == RQ_DONE;
+    if (q->state == RQ_DONE) {
         if (expval) *expval = q->result;
         if (latency_us) *latency_us = (q->t_done - q->t_submit) * 1e6;
         if (q->status != PP_OK) return fail(q->status, "request failed");
@@ -2160,7 +2547,7 @@ extern "C" pp_status pp_server_poll(pp_server *S, int64_t ticket, int32_t *done,
 extern "C" pp_status pp_server_drain(pp_server *S) {
     if (!S) return fail(PP_ERR_INVALID, "null server");
     std::unique_lock<std::mutex> lk(S->mu);
-    S->done_cv.wait(lk, [&] { return S->queue.empty() && S->active.empty(); });
+    S->done_cv.wait(lk, [&] { return server_idle(S); });
     return PP_OK;
 }
 
@@ -2174,13 +2561,24 @@ extern "C" pp_status pp_server_counters(pp_server *S, int64_t *iterations, int64
     return PP_OK;
 }
 
+extern "C" pp_status pp_server_pool_bytes(pp_server *S, int64_t *held, int64_t *peak) {
+    if (!S) return fail(PP_ERR_INVALID, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (held) *held = S->pool_held;
+    if (peak) *peak = S->pool_peak;
+    return PP_OK;
+}
+
 extern "C" void pp_server_destroy(pp_server *S) {
     if (!S) return;
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
         S->cv.notify_all();
+        S->prep_cv.notify_all();
     }
+    for (auto &t : S->preps)
+        if (t.joinable()) t.join();
     if (S->th.joinable()) S->th.join();
     (void)hipStreamSynchronize(S->main);
     (void)hipStreamSynchronize(S->side);
@@ -2191,14 +2589,15 @@ extern "C" void pp_server_destroy(pp_server *S) {
     }
     for (auto &R : S->ring) {
         if (R.ev) (void)hipEventDestroy(R.ev);
-        if (R.d) (void)hipFree(R.d);
+        dev_free(R.d);
         if (R.h) (void)hipHostFree(R.h);
     }
-    (void)hipFree(S->d_results);
+    for (auto &kv : S->pool_free) dev_free(kv.second);
+    dfree(S->d_results);
     (void)hipHostFree(S->h_results);
     for (auto &Ln : S->lane) {
         if (Ln.ev) (void)hipEventDestroy(Ln.ev);
-        if (Ln.d) (void)hipFree(Ln.d);
+        dev_free(Ln.d);
         if (Ln.h) (void)hipHostFree(Ln.h);
         (void)hipStreamDestroy(Ln.st);
     }

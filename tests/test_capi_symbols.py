@@ -52,6 +52,29 @@ def test_version_and_null_safety_without_gpu():
     assert lib.pp_get_truncation(None, None, ctypes.byref(v)) == L.PP_ERR_INVALID
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpauliprop.so not built")
+def test_boundary_entry_points_reject_bad_arguments_without_gpu():
+    """Allocator hook, memory query, parameter-shift gradient and the serving
+    controls validate their arguments before touching a device."""
+    from paper_2502_10685_amd import _lib as L
+    lib = L.load()
+    half = L.PPAllocator(L.ALLOC_FN(lambda n, s, u: None), ctypes.cast(None, L.FREE_FN), None)
+    assert lib.pp_set_allocator(ctypes.byref(half)) == L.PP_ERR_INVALID
+    assert b"alloc and free" in lib.pp_last_error()
+    assert lib.pp_set_allocator(None) == L.PP_OK  # the default pool
+    b, n = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    assert lib.pp_memory_in_use(ctypes.byref(b), ctypes.byref(n)) == L.PP_OK
+    assert b.value >= 0 and n.value >= 0
+    assert lib.pp_memory_in_use(None, None) == L.PP_ERR_INVALID
+    assert lib.pp_psr_gradient(None, None, None) == L.PP_ERR_INVALID
+    assert lib.pp_server_set_queue_limit(None, 4) == L.PP_ERR_INVALID
+    assert lib.pp_server_pool_bytes(None, None, None) == L.PP_ERR_INVALID
+    t = ctypes.c_int64(0)
+    assert lib.pp_server_submit(None, None, ctypes.byref(t)) == L.PP_ERR_INVALID
+    assert lib.pp_evaluate_batch(None, -1, None, None) == L.PP_ERR_INVALID
+    lib.pp_server_destroy(None)  # NULL-safe
+
+
 def test_stats_struct_layout_matches_header():
     from paper_2502_10685_amd import _lib as L
     assert ctypes.sizeof(L.PPStats) == 7 * 8 + 4 * 4

@@ -97,7 +97,8 @@ def test_density_matrix_paper_chain_workload(api):
     wc = W.chain_zxz_circuit()
     _say(f"density {wc.name} m={wc.m}")
     c = api.Circuit.from_workload(wc)
-    _check(c.density_matrix().cpu().numpy(), _rho_sv(wc), 1e-11)
+    err = _check(c.density_matrix().cpu().numpy(), _rho_sv(wc), TOL64)
+    _say(f"density {wc.name}: max |rho - psi psi^dag| = {err:.2e}")
     c.close()
 
 
@@ -110,7 +111,8 @@ def test_density_matrix_paper_sweep_points(api, n, layers, repeats):
     wc = W.chain_zxz_circuit(seed=1000 * n + layers + repeats, n=n, layers=layers, repeats=repeats)
     _say(f"density sweep n={n} layers={layers} repeats={repeats} m={wc.m}")
     c = api.Circuit.from_workload(wc)
-    _check(c.density_matrix().cpu().numpy(), _rho_sv(wc), 1e-11)
+    err = _check(c.density_matrix().cpu().numpy(), _rho_sv(wc), TOL64)
+    _say(f"density sweep n={n} layers={layers} repeats={repeats}: max error {err:.2e}")
     c.close()
 
 

@@ -98,6 +98,45 @@ def test_autograd_binding(api):
     assert float(f2.item()) == pytest.approx(float(f.item()), abs=1e-12)
 
 
+def test_autograd_forward_runs_no_gradient(api):
+    """The forward evaluates <O> only; the adjoint sweep runs in backward
+    (its forward-sweep kernels are timed as tile passes: none before
+    backward).  A CPU angle tensor that requires grad gets its gradient on
+    the CPU."""
+    import torch
+    from paper_2502_10685_amd import _lib as L
+    wc = W.hea_circuit(18, 5, 3, W.obs_tfim(5))
+    c = api.Circuit.from_workload(wc)
+    theta = torch.tensor(wc.theta, requires_grad=True)  # CPU
+    L.profile_enable(True)
+    L.profile_read()
+    f = api.expval(c, theta, 6)
+    torch.cuda.synchronize()
+    fwd = L.profile_read()
+    assert "tile_pass" not in fwd and "resident" in fwd, fwd
+    f.backward()
+    torch.cuda.synchronize()
+    bwd = L.profile_read()
+    L.profile_enable(False)
+    assert "tile_pass" in bwd, bwd
+    assert theta.grad.device.type == "cpu"
+    assert np.max(np.abs(theta.grad.numpy() - oracle.psr_gradient(wc))) <= TOL_PSR
+    assert abs(float(f.item()) - oracle.expval_sv(wc)) <= 1e-12
+
+
+def test_autograd_backward_uses_the_forward_angles(api):
+    """Angles changed on the circuit between forward and backward do not
+    change the gradient of the recorded forward."""
+    import torch
+    wc = W.hea_circuit(19, 4, 2, W.obs_tfim(4))
+    c = api.Circuit.from_workload(wc)
+    theta = torch.tensor(wc.theta, device="cuda", requires_grad=True)
+    f = api.expval(c, theta)
+    c.set_theta(np.zeros(wc.n_params))
+    f.backward()
+    assert np.max(np.abs(theta.grad.cpu().numpy() - oracle.psr_gradient(wc))) <= TOL_PSR
+
+
 def test_gradient_rejects_other_engines(api):
     from paper_2502_10685_amd._lib import PauliPropError
     wc = W.config1()

@@ -105,6 +105,37 @@ def test_tiled_dense_vs_oracle(api, n, k):
         c.close()
 
 
+@pytest.mark.parametrize("k", [5, 6, 7])
+def test_tiled_dense_n11(api, k):
+    """n = 11 (4^11 slots, past the batch workload's n <= 10): 2,500 random
+    gates against the FP64 state vector for every tile size, solo and
+    batched with smaller circuits; the last 175 gates, tracked, against the
+    scalar propagator string for string (tens of thousands to half a million
+    strings)."""
+    rng = np.random.default_rng(1100 + k)
+    wc = W.random_circuit(rng, 11, 2500, W.obs_random_2local(rng, 11))
+    _say(f"tiled n=11 k={k} m={wc.m}")
+    sv = oracle.expval_sv(wc)
+    c, ev = _run(api, wc, engine="dense", tile_qubits=k)
+    st = c.stats()
+    assert st["tile_qubits"] == k and st["passes"] >= 2
+    assert abs(ev - sv) <= TOL64, (ev, sv)
+    others = [W.random_circuit(rng, n, 700, W.obs_z(n, [0, 1])) for n in (8, 10, 11)]
+    cs = [c] + [api.Circuit.from_workload(w, tile_qubits=k) for w in others]
+    out = api.evaluate_batch(cs).cpu().numpy()
+    assert out[0] == ev
+    for w, v in zip(others, out[1:]):
+        assert abs(v - oracle.expval_sv(w)) <= TOL64
+    pre = W.make_circuit(11, (wc.op[-175:], wc.q0[-175:], wc.q1[-175:], wc.param[-175:]), wc.n_params,
+                         (wc.obs_x, wc.obs_z, wc.obs_c), wc.theta)
+    want = oracle.propagate(pre)
+    ct, evt = _run(api, pre, engine="dense", track=True, tile_qubits=k)
+    assert abs(evt - want.expval) <= TOL64
+    _check_set(ct, want)
+    for o in cs + [ct]:
+        o.close()
+
+
 def test_sparse_n8_ragged(api):
     rng = np.random.default_rng(77)
     wc = W.random_circuit(rng, 8, 120, W.obs_z(8, [0, 3]))

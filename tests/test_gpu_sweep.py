@@ -72,7 +72,7 @@ def test_psr_gradient_shared_parameter(api):
              np.array([0, 0], np.int32))
     wc = W.make_circuit(1, gates, 1, W.obs_z(1, [0]), [0.4])
     c = api.Circuit.from_workload(wc)
-    g = c.psr_gradient(wc.theta).numpy()
+    g = c.psr_gradient(wc.theta).cpu().numpy()
     assert abs(g[0] + 2 * math.sin(0.8)) <= 1e-14
 
 
@@ -83,7 +83,7 @@ def test_psr_gradient_config4_matches_adjoint_and_oracle(api):
     wc = W.config4()
     c = api.Circuit.from_workload(wc)
     print("psr sweep config4", flush=True)
-    g_psr = c.psr_gradient(wc.theta).numpy()
+    g_psr = c.psr_gradient(wc.theta).cpu().numpy()
     _, g_adj = c.gradient(5 * 32)
     g_adj = g_adj.cpu().numpy()
     assert np.max(np.abs(g_psr - g_adj)) <= 1e-10

@@ -381,6 +381,52 @@ def test_updates_count_definition():
     assert r.updates == 1 + 2 and len(r.c) == 2
 
 
+def test_updates_count_hand_computed_mixed_circuit():
+    """U on a circuit that mixes Clifford gates and rotations, worked out by
+    hand in Heisenberg order (last gate first), with O = Z on qubit 1 and the
+    gates RX_0(a), CX(0->1), H_1, RY_1(b), S_0 in application order:
+      S_0 sees {IZ} (1), RY_1 splits it into {IZ, IX} (1 entering),
+      H_1 maps it to {IX, IZ} (2), CX maps IZ to ZZ (2), RX_0 splits ZZ into
+      {ZZ, YZ} (2 entering): U = 1 + 1 + 2 + 2 + 2 = 8, final set
+      {IX: cos b, ZZ: -sin b cos a, YZ: -sin b sin a}, so <O> = -sin b cos a
+      (the Bloch vector of qubit 1 after H is (cos a, 0, 0), rotated by b
+      about Y).  A counter that skipped the Clifford gates would give 5, one
+      that counted the set leaving each gate 10."""
+    a, b = 0.7, 1.1
+    c = _letters_circ(2, [(3, 0, -1), (2, 0, 1), (0, 1, -1), (4, 1, -1), (1, 0, -1)], [a, b], "IZ")
+    r = oracle.propagate(c)
+    assert r.updates == 8 and len(r.c) == 3
+    want = {(2, 0): math.cos(b), (0, 3): -math.sin(b) * math.cos(a), (1, 3): -math.sin(b) * math.sin(a)}
+    got = r.as_dict()
+    assert set(got) == set(want)
+    for k, v in want.items():
+        assert abs(got[k] - v) < 1e-15, (k, got[k], v)
+    assert abs(r.expval + math.sin(b) * math.cos(a)) < 1e-15
+
+
+def test_updates_count_hand_computed_with_merge():
+    """Children that land on strings already in the set are merged before the
+    next gate counts the set.  n = 1, O = Z, gates RX(a), RZ(c), RY(b):
+    RY splits Z into {Z, X} (1 entering), RZ splits X into {X, Y} (2
+    entering: {Z, X, Y}), RX splits Z and Y into each other (3 entering), and
+    the children merge into the existing Z and Y, so U = 1 + 2 + 3 = 6 with 3
+    strings at the end (5 without the merge).  Weights by hand:
+      X: -sin b cos c,
+      Z: cos b cos a - sin b sin c sin a,
+      Y: sin b sin c cos a + cos b sin a."""
+    a, cc, b = 0.3, 0.5, 0.9
+    c = _letters_circ(1, [(3, 0, -1), (5, 0, -1), (4, 0, -1)], [a, cc, b], "Z")
+    r = oracle.propagate(c)
+    assert r.updates == 6 and len(r.c) == 3
+    want = {(1, 0): -math.sin(b) * math.cos(cc),
+            (0, 1): math.cos(b) * math.cos(a) - math.sin(b) * math.sin(cc) * math.sin(a),
+            (1, 1): math.sin(b) * math.sin(cc) * math.cos(a) + math.cos(b) * math.sin(a)}
+    got = r.as_dict()
+    assert set(got) == set(want)
+    for k, v in want.items():
+        assert abs(got[k] - v) < 1e-15, (k, got[k], v)
+
+
 # ----------------------------------------------------------------- gradients
 def test_psr_and_fd_match_closed_form():
     for t in (0.2, 1.3, 3.0):
