@@ -196,6 +196,25 @@ PP_API pp_status pp_circuit_set_observable(pp_circuit *c, int64_t n_terms, const
  * for an unknown key or a value out of range (the circuit unchanged). */
 PP_API pp_status pp_circuit_set_option(pp_circuit *c, pp_option key, int64_t value);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * evaluation as pp_evaluate for a DENSE circuit without term tracking, with
+ * the same result bit for bit, but every working buffer (the 4^n weights,
+ * the composed per-wire maps, the launch descriptors) in a static device
+ * array of the library, 24 MiB per device, held until the process ends.
+ * The call allocates nothing and copies nothing from the host: it enqueues
+ * kernel launches on `stream` only.  It reads the circuit's schedule from the
+ * device, so the circuit must have been evaluated once with pp_evaluate (or
+ * pp_evaluate_batch, or served) since its gates, observable or options last
+ * changed: PP_ERR_STATE otherwise, and for SPARSE or tracked circuits.
+ * PP_ERR_CAPACITY when the working set does not fit the array (4^n weights
+ * plus 72 bytes per map plus 80 bytes per pass: n <= 10 in FP64, n <= 11 in
+ * FP32).  The circuit's own weights are left as they were.  Every call on
+ * one device shares that device's array, which keeps the last call's
+ * contents (each call rewrites all it reads): calls that overlap on one
+ * device race, so enqueue them on one stream or serialize them. */
+PP_API pp_status pp_evaluate_noalloc(pp_circuit *c, void *stream, double *d_expval);
+
 /* Enqueues one evaluation of <O> = <0...0| U^dag O U |0...0> (measurement
  * of Sec. II-A from the propagated strings: only strings of I and Z have a
  * nonzero expectation in |0...0>); d_expval is caller-owned device memory

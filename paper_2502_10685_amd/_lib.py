@@ -69,6 +69,7 @@ def load():
         "pp_circuit_set_observable": (st, [P, I64, P, P, P]),
         "pp_circuit_set_option": (st, [P, ctypes.c_int, I64]),
         "pp_evaluate": (st, [P, P, P]),
+        "pp_evaluate_noalloc": (st, [P, P, P]),
         "pp_evaluate_batch": (st, [P, I64, P, P]),
         "pp_evaluate_thetas": (st, [P, I64, P, I32, P, P]),
         "pp_gradient": (st, [P, P, I32, P, P]),

@@ -194,6 +194,70 @@ __global__ void compact_to_sparse_count_kernel(const unsigned long long *total, 
     }
 }
 
+// ------------------------------------------- evaluation without allocation
+// Working set of pp_evaluate_noalloc: a static device array (one per device,
+// held until the process ends).  In host code `scratch` names a host-side
+// stand-in, so its device address is resolved once per device with
+// hipGetSymbolAddress and only that address is passed to kernels.
+constexpr size_t kNoAllocBytes = (size_t)24 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kScratchDevices = 64;
+unsigned char *g_scratch_dev[kScratchDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (resolved once per
+// device, with that device current: at the first pp_circuit_create there).
+pp_status scratch_address(unsigned char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PP_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kScratchDevices) return fail(PP_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PP_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return PP_OK;
+}
+
+
+// Copies a circuit's device descriptors into the scratch array with their
+// weight, map and result pointers redirected into it (no host copy: the
+// launch sequence stays kernels only).
+__global__ void noalloc_patch_kernel(const pp::ComposeDesc *comp_in, pp::ComposeDesc *comp_out,
+                                     const pp::TilePassDesc *pass_in, pp::TilePassDesc *pass_out, int npass,
+                                     const pp::ResidentDesc *res_in, pp::ResidentDesc *res_out, void *coef,
+                                     double *maps, double *expval) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && comp_in) {
+        pp::ComposeDesc d = *comp_in;
+        d.maps = maps;
+        *comp_out = d;
+    }
+    if (i == 0 && res_in) {
+        pp::ResidentDesc d = *res_in;
+        d.coef_in = nullptr;
+        d.coef_out = nullptr;
+        d.pres_out = nullptr;
+        d.maps = maps;
+        d.expval_out = expval;
+        d.counters = nullptr;
+        *res_out = d;
+    }
+    if (i < npass) {
+        pp::TilePassDesc d = pass_in[i];
+        d.coef = coef;
+        d.pres = nullptr;
+        d.maps = maps;
+        d.counters = nullptr;
+        pass_out[i] = d;
+    }
+}
+
 constexpr int kResidentMaxN = 7;
 constexpr int kDenseMaxN = 16;
 constexpr int kDensityMaxN = 12;
@@ -835,6 +899,14 @@ pp_status pp_circuit_create(int32_t n_qubits, pp_dtype dtype, pp_engine engine, 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(PP_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    {
+        // set-up of this device: the address of the static working array of
+        // pp_evaluate_noalloc, resolved here so that the entry point itself
+        // only reads it
+        unsigned char *sp = nullptr;
+        pp_status r = scratch_address(&sp);
+        if (r != PP_OK) return r;
+    }
     pp_circuit *c = new (std::nothrow) pp_circuit();
     if (!c) return fail(PP_ERR_NOMEM, "host allocation");
     c->n = n_qubits;
@@ -1087,6 +1159,63 @@ pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval) {
     if (r != PP_OK) return r;
     c->evaluated = true;
     c->last_track = c->track;
+    return PP_OK;
+}
+
+// pp_evaluate with the working set in the static scratch array: the
+// circuit's device schedule (ops, recipes, descriptors) is read, its weights
+// and maps are not touched; every launch takes the scratch address.
+pp_status pp_evaluate_noalloc(pp_circuit *c, void *stream, double *d_expval) {
+    pp_status r = check_ready(c);
+    if (r != PP_OK) return r;
+    if (!d_expval) return fail(PP_ERR_INVALID, "d_expval is NULL");
+    if (c->engine != PP_ENGINE_DENSE || c->track)
+        return fail(PP_ERR_STATE, "pp_evaluate_noalloc runs DENSE circuits without term tracking");
+    if (!c->plan_valid || c->plan_track != 0 || c->plan_k != tile_qubits_for(c))
+        return fail(PP_ERR_STATE, "the circuit's schedule is not on the device: evaluate it once with "
+                                  "pp_evaluate (or serve it) after its last change");
+    const pp::DensePlan &P = c->dplan;
+    unsigned char *base = nullptr;
+    if ((r = scratch_address(&base)) != PP_OK) return r;
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t npass = P.resident ? 0 : P.passes.size();
+    const size_t off_comp = 0;
+    const size_t off_res = up(sizeof(pp::ComposeDesc));
+    const size_t off_pass = off_res + up(sizeof(pp::ResidentDesc));
+    const size_t off_maps = off_pass + up(npass * sizeof(pp::TilePassDesc));
+    const size_t off_coef = off_maps + up((size_t)9 * sizeof(double) * std::max(P.nmaps(), 1));
+    const size_t coef_bytes = P.resident ? 0 : (size_t)dense_slots(c->n) * c->dbytes;
+    if (off_coef + coef_bytes > kNoAllocBytes)
+        return fail(PP_ERR_CAPACITY, "pp_evaluate_noalloc: working set of " + std::to_string(off_coef + coef_bytes) +
+                                         " bytes exceeds the " + std::to_string(kNoAllocBytes) + "-byte array");
+    hipStream_t s = (hipStream_t)stream;
+    pp::ComposeDesc *comp = (pp::ComposeDesc *)(base + off_comp);
+    pp::ResidentDesc *res = (pp::ResidentDesc *)(base + off_res);
+    pp::TilePassDesc *pass = (pp::TilePassDesc *)(base + off_pass);
+    double *maps = (double *)(base + off_maps);
+    void *coef = base + off_coef;
+    const int pblocks = (int)std::max<size_t>(1, (npass + 255) / 256);
+    hipLaunchKernelGGL(noalloc_patch_kernel, dim3(pblocks), dim3(256), 0, s, c->d_comp, comp,
+                       P.resident ? nullptr : c->d_pass, pass, (int)npass, P.resident ? c->d_res : nullptr, res, coef,
+                       maps, d_expval);
+    HIPCHK(hipGetLastError());
+    if (P.nmaps() > 0) HIPCHK(pp::launch_compose(comp, 1, s, P.nmaps()));
+    if (P.resident) {
+        HIPCHK(pp::launch_resident(res, 1, c->n, c->dbytes, false, s));
+        return PP_OK;
+    }
+    HIPCHK(pp::launch_dense_init(coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+    const int shift = 2 * (c->n - P.k);
+    for (size_t p = 0; p < npass; ++p) {
+        pp::TileGroups grp{};
+        grp.ngroups = 1;
+        grp.first_block[0] = 0;
+        grp.first_block[1] = 1 << shift;
+        grp.first_desc[0] = (int32_t)p;
+        grp.shift[0] = shift;
+        HIPCHK(pp::launch_tile_pass(pass, grp, P.k, c->dbytes, false, s));
+    }
+    HIPCHK(pp::launch_dense_readout(coef, c->n, c->dbytes, d_expval, s));
     return PP_OK;
 }
 
