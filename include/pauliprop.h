@@ -68,7 +68,11 @@ typedef enum pp_dtype { PP_F64 = 0, PP_F32 = 1 } pp_dtype;
  *          index(P) of a 4^n array (the paper's lambda vector indexed
  *          0 ... 4^n - 1, Sec. III-B), so merging duplicates is implicit.
  *          Practical for n <= 13.
- *  SPARSE: an explicit list of (x, z, weight) in struct-of-arrays form;
+ *  SPARSE: an explicit list of weighted strings.  Exact runs with n <= 31
+ *          propagate in the Clifford frame: Clifford gates are folded on the
+ *          host into the axis of the next rotation (a multi-qubit Pauli),
+ *          so the stored strings never move and a rotation splits them in
+ *          one kernel, pairing duplicates through a hash index.  Otherwise
  *          each pass applies a run of Clifford gates and one rotation,
  *          appends the split strings by wave-ballot compaction, then merges
  *          duplicates with a radix sort and a segmented FP64 sum.
@@ -92,7 +96,15 @@ typedef enum pp_option {
                                for pp_gradient (the whole Heisenberg + adjoint
                                sweep, a training step's launch sequence);
                                theta is read from device memory at replay */
-    PP_OPT_BLOCK = 4        /* threads per workgroup (64..1024), 0 = default */
+    PP_OPT_BLOCK = 4,       /* threads per workgroup (64..1024), 0 = default */
+    PP_OPT_SPARSE_FRAME = 5 /* SPARSE, exact runs with n <= 31: 1 (default)
+                               propagates in the Clifford frame (Clifford
+                               gates folded into the rotation axes on the
+                               host, one kernel per rotation, duplicates
+                               found through a hash index); 0 uses the
+                               sort-merge pass of every rotation.  Same
+                               strings and weights; truncated runs and
+                               n > 31 always use sort-merge */
 } pp_option;
 
 typedef struct pp_circuit pp_circuit;
@@ -428,6 +440,23 @@ PP_API pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *
                                     const int32_t *q1, const int32_t *param, int32_t n_params, int32_t k,
                                     int32_t compose, int32_t reorder, int64_t *n_ops, int64_t *n_passes,
                                     int32_t *pass_ops, int64_t max_passes);
+
+/* Host-only introspection of the Clifford frame of a SPARSE schedule (no
+ * device needed; n in [1, 31]): the sparse passes (in Heisenberg order, each
+ * a run of Clifford gates closed by a rotation, or the trailing Clifford
+ * gates) and for each the axis of its rotation in the stored frame, P = D
+ * sigma D^dag with D the Clifford gates processed so far (Table I's
+ * rotation rows conjugated by D): pmask[i] = its Pauli string packed as
+ * (z << n) | x, sign[i] = +-1 with P = sign * that Hermitian Pauli,
+ * rot_param[i] (-1 for the trailing Clifford gates), ngates[i]; xrows (n
+ * entries, optional): bit j of the x part of a stored string's actual form
+ * after every Clifford is the parity of its packed key masked by xrows[j].
+ * Arrays of capacity max_passes; *n_passes receives the count.  Same
+ * validation as pp_circuit_load_gates. */
+PP_API pp_status pp_plan_sparse_frame(int32_t n_qubits, int64_t m, const uint8_t *op, const int32_t *q0,
+                                      const int32_t *q1, const int32_t *param, int32_t n_params, int64_t max_passes,
+                                      uint64_t *pmask, int32_t *sign, int32_t *rot_param, int32_t *ngates,
+                                      uint64_t *xrows, int64_t *n_passes);
 
 /* Kernel timing for measurement (the stage timings of Sec. V, taken with
  * HIP events): while enabled (on = 1), the library's

@@ -12,7 +12,7 @@ STATUS_NAMES = ["PP_OK", "PP_ERR_INVALID", "PP_ERR_NOMEM", "PP_ERR_DEVICE", "PP_
                 "PP_ERR_STATE", "PP_ERR_BUSY"]
 PP_F64, PP_F32 = 0, 1
 PP_ENGINE_AUTO, PP_ENGINE_DENSE, PP_ENGINE_SPARSE = 0, 1, 2
-PP_OPT_TRACK_TERMS, PP_OPT_TILE_QUBITS, PP_OPT_MAX_TERMS, PP_OPT_USE_GRAPH, PP_OPT_BLOCK = range(5)
+PP_OPT_TRACK_TERMS, PP_OPT_TILE_QUBITS, PP_OPT_MAX_TERMS, PP_OPT_USE_GRAPH, PP_OPT_BLOCK, PP_OPT_SPARSE_FRAME = range(6)
 PP_TUNE_TILE_QUBITS, PP_TUNE_TILE_KERNEL, PP_TUNE_RESIDENT_BLOCK = 0, 1, 2
 
 
@@ -92,6 +92,7 @@ def load():
         "pp_server_destroy": (None, [P]),
         "pp_plan_dense_info": (st, [I32, I64, P, P, P, P, I32, I32, I32, I32, ctypes.POINTER(I64),
                                     ctypes.POINTER(I64), P, I64]),
+        "pp_plan_sparse_frame": (st, [I32, I64, P, P, P, P, I32, I64, P, P, P, P, P, ctypes.POINTER(I64)]),
         "pp_tune_set": (st, [ctypes.c_int, I32, I32]),
         "pp_tune_get": (st, [ctypes.c_int, I32, ctypes.POINTER(I32)]),
         "pp_profile_enable": (st, [I32]),
@@ -141,6 +142,30 @@ def plan_dense_info(n, op, q0, q1, param, n_params, k, compose=True, reorder=Tru
     if want_passes:
         return nops.value, npass.value, buf[: npass.value].copy()
     return nops.value, npass.value
+
+
+def plan_sparse_frame(n, op, q0, q1, param, n_params):
+    """Host-side Clifford frame of a SPARSE schedule: per pass (pmask, sign,
+    rot_param, ngates) and the n x-rows of the final frame."""
+    import numpy as np
+    op = np.ascontiguousarray(op, dtype=np.uint8)
+    q0 = np.ascontiguousarray(q0, dtype=np.int32)
+    q1 = np.ascontiguousarray(q1, dtype=np.int32)
+    param = np.ascontiguousarray(param, dtype=np.int32)
+    cap = int(op.shape[0]) + 1
+    pm = np.zeros(cap, np.uint64)
+    sg = np.zeros(cap, np.int32)
+    rp = np.zeros(cap, np.int32)
+    ng = np.zeros(cap, np.int32)
+    xr = np.zeros(max(int(n), 1), np.uint64)
+    npass = ctypes.c_int64(0)
+    P = ctypes.c_void_p
+    check(load().pp_plan_sparse_frame(int(n), int(op.shape[0]), op.ctypes.data_as(P), q0.ctypes.data_as(P),
+                                      q1.ctypes.data_as(P), param.ctypes.data_as(P), int(n_params), cap,
+                                      pm.ctypes.data_as(P), sg.ctypes.data_as(P), rp.ctypes.data_as(P),
+                                      ng.ctypes.data_as(P), xr.ctypes.data_as(P), ctypes.byref(npass)))
+    k = npass.value
+    return pm[:k], sg[:k], rp[:k], ng[:k], xr[:n]
 
 
 def memory_in_use():

@@ -453,6 +453,15 @@ struct pp_circuit {
     // sparse buffers
     pp::SparseBuffers sb{};
     void *sb_base[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // Clifford-frame engine (exact SPARSE runs with n <= 31): string list,
+    // hash index, counters; its plan and the x rows of the final frame
+    int frame_opt = 1;           // PP_OPT_SPARSE_FRAME
+    pp::FrameBuffers fb{};
+    pp::FramePlan fplan;
+    uint64_t *d_xrows = nullptr;
+    bool plan_frame = false;     // the plan's engine: frame (true) or sort-merge
+    bool frame_ran = false;      // the last SPARSE evaluation used the frame
+    bool frame_terms = false;    // sb holds the frame run's full final set
     uint32_t *d_codes = nullptr;
     double *d_partials = nullptr;
 
@@ -546,6 +555,7 @@ void free_plan_buffers(pp_circuit *c) {
     dfree(c->d_res);
     dfree(c->d_comp);
     dfree(c->d_codes);
+    dfree(c->d_xrows);
     c->plan_valid = false;
 }
 
@@ -585,6 +595,12 @@ void free_state_buffers(pp_circuit *c) {
     dfree(c->sb.tile_flags);
     dfree(c->d_dropped);
     c->sb = pp::SparseBuffers{};
+    dfree(c->fb.keys);
+    dev_free(c->fb.coef);
+    dfree(c->fb.index);
+    dfree(c->fb.cnt);
+    dfree(c->fb.updates);
+    c->fb = pp::FrameBuffers{};
 }
 
 int64_t dense_slots(int n) { return (int64_t)1 << (2 * n); }
@@ -648,6 +664,31 @@ pp_status ensure_state(pp_circuit *c, bool weights = true) {
         HIPCHK(dalloc(&c->d_dropped, (size_t)tiles + 1));
         HIPCHK(dalloc(&c->d_partials, 256));
     }
+    if (c->engine == PP_ENGINE_SPARSE && c->n <= pp::kFrameMaxN && c->frame_opt && !c->fb.keys) {
+        // index slots: a power of two of at least twice the list capacity
+        const int64_t cap = c->sb.cap2 / 2;
+        int bits = 1;
+        while (((int64_t)1 << bits) < 2 * cap) ++bits;
+        pp::FrameBuffers f{};
+        f.cap = cap;
+        f.slots = (int64_t)1 << bits;
+        f.slot_bits = bits;
+        f.n = c->n;
+        hipError_t e = dalloc(&f.keys, (size_t)cap);
+        if (e == hipSuccess) e = dev_alloc(&f.coef, (size_t)cap * c->dbytes);
+        if (e == hipSuccess) e = dalloc(&f.index, (size_t)(2 * f.slots));
+        if (e == hipSuccess) e = dalloc(&f.cnt, 8);
+        if (e == hipSuccess) e = dalloc(&f.updates, 1);
+        if (e != hipSuccess) {
+            dfree(f.keys);
+            dev_free(f.coef);
+            dfree(f.index);
+            dfree(f.cnt);
+            dfree(f.updates);
+            return fail(PP_ERR_NOMEM, "Clifford-frame buffers");
+        }
+        c->fb = f;
+    }
     if (!c->d_counters) HIPCHK(dalloc(&c->d_counters, 4));
     if (!c->d_result) HIPCHK(dalloc(&c->d_result, 1));
     return PP_OK;
@@ -661,17 +702,31 @@ pp_status upload_vec(T **dptr, const std::vector<T> &v) {
     return PP_OK;
 }
 
+// The Clifford-frame engine serves exact SPARSE evaluations with n <= 31;
+// truncated runs and larger n take the sort-merge engine.
+bool wants_frame(const pp_circuit *c) {
+    return c->engine == PP_ENGINE_SPARSE && c->frame_opt && c->n <= pp::kFrameMaxN && c->trunc_eps == 0.0 &&
+           c->trunc_w >= c->n && c->fb.keys;
+}
+
 pp_status ensure_plan(pp_circuit *c, bool weights = true) {
     pp_status r = ensure_state(c, weights);
     if (r != PP_OK) return r;
     const int k = c->engine == PP_ENGINE_DENSE ? tile_qubits_for(c) : 0;
+    const bool frame = wants_frame(c);
     // the descriptors hold the weight pointer they were built with
-    if (c->plan_valid && c->plan_track == c->track && c->plan_k == k && c->plan_coef == c->coef) return PP_OK;
+    if (c->plan_valid && c->plan_track == c->track && c->plan_k == k && c->plan_coef == c->coef &&
+        c->plan_frame == frame)
+        return PP_OK;
     free_plan_buffers(c);
     if (c->track && c->engine == PP_ENGINE_DENSE && !c->pres) HIPCHK(dalloc(&c->pres, (size_t)dense_slots(c->n)));
     if (c->engine == PP_ENGINE_SPARSE) {
         c->splan = pp::plan_sparse(c->g);
         if ((r = upload_vec(&c->d_codes, c->splan.codes)) != PP_OK) return r;
+        if (frame) {
+            c->fplan = pp::plan_frame(c->g, c->splan);
+            if ((r = upload_vec(&c->d_xrows, c->fplan.xrows)) != PP_OK) return r;
+        }
     } else {
         c->dplan = pp::plan_dense(c->g, k, kLowQubits, c->track == 0, c->track == 0);
         const pp::DensePlan &P = c->dplan;
@@ -734,6 +789,7 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
     c->plan_track = c->track;
     c->plan_k = k;
     c->plan_coef = c->coef;
+    c->plan_frame = frame;
     c->plan_gen = ++g_plan_gen;
     return PP_OK;
 }
@@ -773,7 +829,10 @@ void fill_plan_stats(pp_circuit *c) {
         int rot = 0;
         for (auto &p : P.passes) rot += p.rot_op >= 3;
         const int dig = (2 * c->n + 7) / 8;
-        s.launches = 2 + 3 * (int64_t)P.passes.size() + (int64_t)(rot + 1) * (3 * dig + 3) + 2;
+        if (c->plan_frame)  // clear + init, one per pass, x0 + sort + readout
+            s.launches = 2 + (int64_t)P.passes.size() + 2 + (3 * dig + 4) + 2;
+        else
+            s.launches = 2 + 3 * (int64_t)P.passes.size() + (int64_t)(rot + 1) * (3 * dig + 3) + 2;
         s.bytes_per_eval = 0;  // known after the run (48 or 40 bytes per update)
     }
 }
@@ -821,7 +880,32 @@ pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
     return PP_OK;
 }
 
+// Exact SPARSE evaluation in the Clifford frame: the observable into the
+// list and index, one kernel per pass, then the strings whose actual form
+// is made of I and Z sorted into canonical order and summed in that order.
+pp_status enqueue_frame(pp_circuit *c, hipStream_t s, double *out) {
+    if ((int64_t)c->ox.size() > c->fb.cap) return fail(PP_ERR_CAPACITY, "observable larger than the term capacity");
+    HIPCHK(pp::launch_frame_init(c->fb, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+    const int np = (int)c->fplan.passes.size();
+    for (int i = 0; i < np; ++i) {
+        ProfScope ps(PC_SPASS, s);
+        HIPCHK(pp::launch_frame_pass(c->fb, c->dbytes, c->fplan.passes[(size_t)i], c->d_theta, i, s));
+    }
+    {
+        ProfScope ps(PC_SMERGE, s);
+        HIPCHK(pp::launch_frame_x0(c->fb, c->dbytes, c->d_xrows, c->d_codes, (int)c->splan.codes.size(), np, c->sb,
+                                   s));
+        HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s));
+    }
+    {
+        ProfScope ps(PC_READOUT, s);
+        HIPCHK(pp::launch_sparse_readout(c->sb, c->dbytes, c->d_partials, out, s));
+    }
+    return PP_OK;
+}
+
 pp_status enqueue_sparse(pp_circuit *c, hipStream_t s, double *out) {
+    if (c->plan_frame) return enqueue_frame(c, s, out);
     const pp::SparsePlan &P = c->splan;
     if ((int64_t)c->ox.size() > c->sb.cap2) return fail(PP_ERR_CAPACITY, "observable larger than the term capacity");
     pp::SparseTrunc tr;
@@ -994,6 +1078,41 @@ pp_status pp_plan_dense_info(int32_t n_qubits, int64_t m, const uint8_t *op, con
     return PP_OK;
 }
 
+pp_status pp_plan_sparse_frame(int32_t n_qubits, int64_t m, const uint8_t *op, const int32_t *q0, const int32_t *q1,
+                               const int32_t *param, int32_t n_params, int64_t max_passes, uint64_t *pmask,
+                               int32_t *sign, int32_t *rot_param, int32_t *ngates, uint64_t *xrows,
+                               int64_t *n_passes) {
+    if (n_qubits < 1 || n_qubits > pp::kFrameMaxN) return fail(PP_ERR_INVALID, "n_qubits must be in [1, 31]");
+    if (!n_passes || (max_passes > 0 && (!pmask || !sign || !rot_param || !ngates)))
+        return fail(PP_ERR_INVALID, "null output");
+    pp_status r = validate_gates(n_qubits, m, op, q0, q1, param, n_params);
+    if (r != PP_OK) return r;
+    pp::GateList g;
+    g.n = n_qubits;
+    g.m = m;
+    g.op.assign(op, op + m);
+    g.q0.assign(q0, q0 + m);
+    g.q1.resize(m);
+    g.param.resize(m);
+    for (int64_t i = 0; i < m; ++i) {
+        g.q1[i] = op[i] == PP_CX ? q1[i] : -1;
+        g.param[i] = op[i] >= PP_RX ? param[i] : -1;
+    }
+    g.n_params = n_params;
+    const pp::SparsePlan sp = pp::plan_sparse(g);
+    const pp::FramePlan F = pp::plan_frame(g, sp);
+    *n_passes = (int64_t)F.passes.size();
+    for (int64_t i = 0; i < max_passes && i < (int64_t)F.passes.size(); ++i) {
+        pmask[i] = F.passes[i].pmask;
+        sign[i] = F.passes[i].sign;
+        rot_param[i] = F.passes[i].rot_param;
+        ngates[i] = F.passes[i].ngates;
+    }
+    if (xrows)
+        for (int j = 0; j < n_qubits; ++j) xrows[j] = F.xrows[(size_t)j];
+    return PP_OK;
+}
+
 pp_status pp_circuit_load_gates(pp_circuit *c, int64_t m, const uint8_t *op, const int32_t *q0, const int32_t *q1,
                                 const int32_t *param, int32_t n_params) {
     if (!c) return fail(PP_ERR_INVALID, "null circuit");
@@ -1109,6 +1228,10 @@ pp_status pp_circuit_set_option(pp_circuit *c, pp_option key, int64_t value) {
         if (value != 0 && (value < 64 || value > 1024 || (value & 63))) return fail(PP_ERR_INVALID, "bad block size");
         c->block = (int)value;
         return PP_OK;
+    case PP_OPT_SPARSE_FRAME:
+        c->frame_opt = value ? 1 : 0;
+        free_graph(c);
+        return PP_OK;
     }
     return fail(PP_ERR_INVALID, "unknown option");
 }
@@ -1159,6 +1282,8 @@ pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval) {
     if (r != PP_OK) return r;
     c->evaluated = true;
     c->last_track = c->track;
+    c->frame_ran = sparse && c->plan_frame;
+    c->frame_terms = false;
     return PP_OK;
 }
 
@@ -1226,8 +1351,18 @@ pp_status pp_get_stats(pp_circuit *c, pp_stats *out) {
         if (c->engine == PP_ENGINE_SPARSE) {
             long long cnt[2] = {0, 0};
             unsigned long long upd = 0;
-            HIPCHK(hipMemcpy(cnt, c->sb.count, sizeof(cnt), hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(&upd, c->sb.updates, sizeof(upd), hipMemcpyDeviceToHost));
+            if (c->frame_ran) {
+                unsigned long long fc[7] = {0, 0, 0, 0, 0, 0, 0};
+                HIPCHK(hipMemcpy(fc, c->fb.cnt, sizeof(fc), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(&upd, c->fb.updates, sizeof(upd), hipMemcpyDeviceToHost));
+                const int ql = pp::frame_slot_of((int)c->fplan.passes.size() - 1);
+                const unsigned long long len = fc[ql] + fc[3 + ql];
+                cnt[0] = (long long)std::min<unsigned long long>(len, (unsigned long long)c->fb.cap);
+                cnt[1] = (fc[6] || len > (unsigned long long)c->fb.cap) ? 1 : 0;
+            } else {
+                HIPCHK(hipMemcpy(cnt, c->sb.count, sizeof(cnt), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(&upd, c->sb.updates, sizeof(upd), hipMemcpyDeviceToHost));
+            }
             c->st.term_updates = (int64_t)upd;
             c->st.final_terms = cnt[0];
             c->st.overflow = (int32_t)cnt[1];
@@ -1260,6 +1395,13 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
     long long count = 0;
     pp_status r = PP_OK;
     if (c->engine == PP_ENGINE_SPARSE) {
+        if (c->frame_ran && !c->frame_terms) {
+            // the actual strings of the frame run, sorted into canonical order
+            HIPCHK(pp::launch_frame_materialize(c->fb, c->dbytes, c->d_codes, (int)c->splan.codes.size(),
+                                                (int)c->fplan.passes.size(), c->sb, s));
+            HIPCHK(pp::launch_sparse_merge(c->sb, c->n, c->dbytes, s));
+            c->frame_terms = true;
+        }
         HIPCHK(hipStreamSynchronize(s));
         long long cnt[2];
         HIPCHK(hipMemcpy(cnt, c->sb.count, sizeof(cnt), hipMemcpyDeviceToHost));
@@ -1408,6 +1550,10 @@ pp_status pp_get_truncation(pp_circuit *c, void *stream, double *dropped_abs) {
     if (!c || !dropped_abs) return fail(PP_ERR_INVALID, "null argument");
     if (c->engine != PP_ENGINE_SPARSE || !c->d_dropped || !c->evaluated)
         return fail(PP_ERR_STATE, "no SPARSE evaluation yet");
+    if (c->frame_ran) {  // exact run: nothing dropped
+        *dropped_abs = 0.0;
+        return PP_OK;
+    }
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     HIPCHK(hipMemcpy(dropped_abs, c->d_dropped + c->sb.max_tiles, sizeof(double), hipMemcpyDeviceToHost));
     return PP_OK;

@@ -613,4 +613,105 @@ SparsePlan plan_sparse(const GateList &g) {
     return P;
 }
 
+// ------------------------------------------------------------ Clifford frame
+namespace {
+
+// i^r X^x Z^z (Pauli operators in product form; r mod 4)
+struct RawPauli {
+    uint64_t x, z;
+    int r;
+};
+
+RawPauli raw_mul(const RawPauli &A, const RawPauli &B) {
+    // X^x1 Z^z1 X^x2 Z^z2 = (-1)^|z1 & x2| X^(x1^x2) Z^(z1^z2)
+    return RawPauli{A.x ^ B.x, A.z ^ B.z, (A.r + B.r + 2 * __builtin_popcountll(A.z & B.x)) & 3};
+}
+
+// Heisenberg image of a Pauli string's bits under one Clifford code (signs
+// not needed here): H swaps x_q and z_q, S^dag . S adds x_q to z_q,
+// CX(a -> b) adds x_a to x_b and z_b to z_a.
+void heis_bits(uint64_t &x, uint64_t &z, uint32_t code) {
+    const int op = code & 0xff, a = (code >> 8) & 0xff, b = (code >> 16) & 0xff;
+    const uint64_t xa = (x >> a) & 1ull, za = (z >> a) & 1ull;
+    if (op == 0) {
+        const uint64_t f = (xa ^ za) << a;
+        x ^= f;
+        z ^= f;
+    } else if (op == 1) {
+        z ^= xa << a;
+    } else {
+        x ^= xa << b;
+        z ^= ((z >> b) & 1ull) << a;
+    }
+}
+
+}  // namespace
+
+FramePlan plan_frame(const GateList &g, const SparsePlan &sp) {
+    const int n = g.n;
+    FramePlan F;
+    // rows of D: DX[j] = D X_j D^dag, DZ[j] = D Z_j D^dag; D starts as the
+    // identity and becomes D g for every Clifford g processed
+    std::vector<RawPauli> DX(n), DZ(n);
+    for (int j = 0; j < n; ++j) {
+        DX[j] = RawPauli{1ull << j, 0, 0};
+        DZ[j] = RawPauli{0, 1ull << j, 0};
+    }
+    for (const SparsePassDesc &p : sp.passes) {
+        for (int i = p.g_begin; i < p.g_end; ++i) {
+            // D g G g^dag D^dag for the generators G that g moves:
+            // H: X <-> Z; S: X -> iXZ; CX(c -> t): X_c -> X_c X_t, Z_t -> Z_c Z_t
+            const uint32_t code = sp.codes[(size_t)i];
+            const int op = code & 0xff, a = (code >> 8) & 0xff, b = (code >> 16) & 0xff;
+            if (op == 0) {
+                std::swap(DX[a], DZ[a]);
+            } else if (op == 1) {
+                RawPauli y = raw_mul(DX[a], DZ[a]);
+                y.r = (y.r + 1) & 3;
+                DX[a] = y;
+            } else {
+                DX[a] = raw_mul(DX[a], DX[b]);
+                DZ[b] = raw_mul(DZ[a], DZ[b]);
+            }
+        }
+        FramePassDesc d{};
+        d.ngates = p.ngates;
+        d.rot_param = -1;
+        if (p.rot_op >= 3) {
+            RawPauli P;
+            if (p.rot_op == 3) {
+                P = DX[p.rot_q];
+            } else if (p.rot_op == 5) {
+                P = DZ[p.rot_q];
+            } else {  // Y = i X Z
+                P = raw_mul(DX[p.rot_q], DZ[p.rot_q]);
+                P.r = (P.r + 1) & 3;
+            }
+            // P = i^r X^x Z^z = i^(r - |x & z|) (Hermitian Pauli of x, z);
+            // the factor is +-1 because P is Hermitian
+            const int a = __builtin_popcountll(P.x & P.z) & 3;
+            const int e = (P.r - a) & 3;
+            d.pmask = (P.z << n) | P.x;
+            d.sign = e == 0 ? 1 : -1;
+            d.a = a;
+            d.rot_param = p.rot_param;
+        }
+        F.passes.push_back(d);
+    }
+    // x part of the actual string D^dag S D of a stored key, bit by bit: the
+    // map is linear in the key bits, so column b is the image of the b-th
+    // generator (x_b for b < n, z_(b-n) above) under every code in order
+    std::vector<uint64_t> colx((size_t)2 * n);
+    for (int b = 0; b < 2 * n; ++b) {
+        uint64_t x = b < n ? 1ull << b : 0, z = b < n ? 0 : 1ull << (b - n);
+        for (uint32_t code : sp.codes) heis_bits(x, z, code);
+        colx[(size_t)b] = x;
+    }
+    F.xrows.assign((size_t)n, 0);
+    for (int j = 0; j < n; ++j)
+        for (int b = 0; b < 2 * n; ++b)
+            if ((colx[(size_t)b] >> j) & 1ull) F.xrows[(size_t)j] |= 1ull << b;
+    return F;
+}
+
 }  // namespace pp

@@ -102,6 +102,15 @@ struct GradPlan {
 GradPlan plan_gradient(const GateList &g, int k_heis, int k_fwd, int low, int64_t every);
 SparsePlan plan_sparse(const GateList &g);
 
+// Clifford frame of a sparse schedule (n <= kFrameMaxN): the rotation axis of
+// every pass in the stored frame, and the rows of the linear map from a
+// stored key to the x part of its actual string after every Clifford.
+struct FramePlan {
+    std::vector<FramePassDesc> passes;  // one per sparse pass
+    std::vector<uint64_t> xrows;        // n masks over the packed key
+};
+FramePlan plan_frame(const GateList &g, const SparsePlan &sp);
+
 // structural 3x3 pattern of one gate's Heisenberg map (bit 3*row + col)
 unsigned gate_smask(int op);
 unsigned smask_compose(unsigned after, unsigned before);

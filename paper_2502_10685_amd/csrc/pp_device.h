@@ -131,6 +131,40 @@ struct SparsePassDesc {
     int32_t ngates;          // Cliffords + rotation (term-update counting)
 };
 
+// Clifford-frame sparse engine (n <= 31, exact propagation).  The Clifford
+// gates are never applied to the strings: the host keeps the accumulated
+// Clifford D (processed gates, Heisenberg order) and the stored set S stands
+// for D^dag S D.  A rotation exp(-i t sigma/2) on qubit q is then a rotation
+// about P = D sigma D^dag in the stored frame (a multi-qubit Pauli with a
+// sign), whose child of an anticommuting S is i sin(t) P S.  Keys are packed
+// as (z << n) | x.
+struct FramePassDesc {
+    uint64_t pmask;     // packed key of P's Pauli string
+    int32_t sign;       // +1 or -1: P = sign * (the Hermitian Pauli of pmask)
+    int32_t a;          // popcount(x & z) of P, mod 4
+    int32_t rot_param;  // -1: no rotation (Clifford gates only)
+    int32_t ngates;     // gates of the pass (term-update counting)
+};
+
+struct FrameBuffers {
+    uint64_t *keys;            // list of stored strings: packed keys
+    void *coef;                // their weights (FP64 or FP32)
+    uint64_t *index;           // hash index, 16-byte slots: [2s] key
+                               // (kFrameEmpty when free), [2s + 1] list position
+    unsigned long long *cnt;   // pass p reads the list length L and child
+                               // count D of pass p - 1 from slot (p-1) mod 3
+                               // ([slot] and [3 + slot]), records its own
+                               // length in slot p mod 3 and counts its
+                               // children in [3 + p mod 3]; [6] overflow
+    unsigned long long *updates;
+    int64_t cap;               // list capacity
+    int64_t slots;             // index slots (power of two, >= 2 cap)
+    int32_t slot_bits;
+    int32_t n;
+};
+constexpr uint64_t kFrameEmpty = ~0ull;
+constexpr int kFrameMaxN = 31;  // 2n key bits below the empty marker
+
 // ------------------------------------------------------------ launchers
 // Dense engine (dense.hip)
 // max_maps: the largest nmaps of the descriptors (sizes the grid; any value
@@ -209,5 +243,24 @@ hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStre
                                const SparseTrunc &tr = SparseTrunc{});
 hipError_t launch_sparse_readout(SparseBuffers &b, int dtype_bytes, double *partials, double *out,
                                  hipStream_t s);
+// Clifford-frame engine (sparse.hip)
+hipError_t launch_frame_init(FrameBuffers &f, int dtype_bytes, const uint64_t *x, const uint64_t *z,
+                             const double *c, int nterms, hipStream_t s);
+// pass: its index in the schedule (selects the counter slots)
+hipError_t launch_frame_pass(FrameBuffers &f, int dtype_bytes, const FramePassDesc &p, const double *theta,
+                             int pass, hipStream_t s);
+// Strings whose actual form D^dag S D (codes: every Clifford in processing
+// order) is made of I and Z only, with their signed weights, into the
+// SparseBuffers list out (x = 0, z, weight as FP64), count into out.count[0]
+// and the frame's overflow flag into out.count[1].  xrows[j]: mask of the key
+// bits whose parity is bit j of the actual x part.
+hipError_t launch_frame_x0(FrameBuffers &f, int dtype_bytes, const uint64_t *xrows, const uint32_t *codes,
+                           int ncodes, int npasses, SparseBuffers &out, hipStream_t s);
+// Every string in its actual form into out (x, z, weight in out's type),
+// count and overflow flag into out.count[0], [1].
+hipError_t launch_frame_materialize(FrameBuffers &f, int dtype_bytes, const uint32_t *codes, int ncodes,
+                                    int npasses, SparseBuffers &out, hipStream_t s);
+// list length after `npasses` passes (the counters of the last one)
+__host__ __device__ inline int frame_slot_of(int pass) { return ((pass % 3) + 3) % 3; }
 
 }  // namespace pp

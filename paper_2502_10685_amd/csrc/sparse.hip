@@ -588,6 +588,308 @@ __global__ void sp_init_kernel(uint64_t *x, uint64_t *z, void *c, long long *cou
     *updates = 0;
 }
 
+// ============================================================ Clifford frame
+// The stored strings never see a Clifford gate: the host folds every
+// Clifford into the frame D and hands each rotation its axis P = D sigma
+// D^dag (FramePassDesc).  A rotation then splits every stored S that
+// anticommutes with P into cos(t) S + i sin(t) P S (Table I's R rows
+// conjugated by D), and i P S = +-(Pauli of key(S) ^ key(P)).  Duplicates
+// are found through a hash index (key -> list position) instead of a sort:
+// S and K = S ^ P anticommute with P together, so when both are present the
+// pair is updated by the thread of the smaller key, and otherwise the child
+// of S is appended.  Every weight is written by one thread from fixed
+// inputs (the sum of two products, rounded as the sort-merge engine rounds
+// it), so results do not depend on scheduling although the list order does.
+__device__ __forceinline__ uint64_t frame_home(uint64_t key, int bits) {
+    return (key * 0x9E3779B97F4A7C15ull) >> (64 - bits);
+}
+
+typedef unsigned long long FrameSlot __attribute__((ext_vector_type(2)));  // key, list position
+
+__device__ __forceinline__ FrameSlot frame_slot(const FrameBuffers &f, uint64_t s) {
+    return *reinterpret_cast<const FrameSlot *>(f.index + 2 * s);
+}
+
+// List position of `key`, or -1, given the slot `e` already read at probe
+// position `s` (its home slot).  Slots only ever go from empty to a key, so
+// an empty slot met on the probe path means the key was never inserted;
+// keys this thread looks up are either older than the kernel or its own.
+__device__ __forceinline__ long long frame_resolve(const FrameBuffers &f, uint64_t key, uint64_t s, FrameSlot e) {
+    const uint64_t mask = (uint64_t)f.slots - 1;
+    for (long long probe = 0; probe < f.slots; ++probe) {
+        if (e.x == key) return (long long)e.y;
+        if (e.x == kFrameEmpty) return -1;
+        s = (s + 1) & mask;
+        e = frame_slot(f, s);
+    }
+    return -1;
+}
+
+__device__ __forceinline__ long long frame_find(const FrameBuffers &f, uint64_t key) {
+    const uint64_t s = frame_home(key, f.slot_bits);
+    return frame_resolve(f, key, s, frame_slot(f, s));
+}
+
+__device__ __forceinline__ void frame_insert(const FrameBuffers &f, uint64_t key, uint64_t pos) {
+    const uint64_t mask = (uint64_t)f.slots - 1;
+    uint64_t s = frame_home(key, f.slot_bits);
+    for (long long probe = 0; probe < f.slots; ++probe) {
+        const unsigned long long prev = atomicCAS((unsigned long long *)(f.index + 2 * s),
+                                                  (unsigned long long)kFrameEmpty, (unsigned long long)key);
+        if (prev == kFrameEmpty || prev == key) {
+            f.index[2 * s + 1] = pos;
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+// Sign of i P S as a multiple of the Hermitian Pauli of key(S) ^ key(P), for
+// anticommuting Hermitian P (packed pmask, a = |x_P & z_P|) and S (packed
+// key), with Y = iXZ: P S = i^(a + b + 2c - d) (Pauli of the XOR), where
+// b = |x_S & z_S|, c = |z_P & x_S| (Z past X), d = |x' & z'| of the result.
+__device__ __forceinline__ double frame_child_sign(uint64_t key, uint64_t pmask, int a, int n) {
+    const uint64_t lo = (1ull << n) - 1ull;
+    const uint64_t xs = key & lo, zs = key >> n, xp = pmask & lo, zp = pmask >> n;
+    const int b = __popcll(xs & zs), c = __popcll(zp & xs), d = __popcll((xs ^ xp) & (zs ^ zp));
+    return ((1 + a + b + 2 * c - d) & 3) == 0 ? 1.0 : -1.0;
+}
+
+// the merged weight of a pair: both products rounded to the storage type,
+// summed in FP64 (the rounding points of the sort-merge engine)
+template <typename T>
+__device__ __forceinline__ double frame_merge2(double p, double q) {
+    return (double)(T)p + (double)(T)q;
+}
+
+__global__ void frame_clear_kernel(uint64_t *__restrict__ index, long long slots) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < slots; i += (long long)gridDim.x * blockDim.x)
+        index[2 * i] = kFrameEmpty;
+}
+
+// The observable into the list and the index (one thread, in term order;
+// repeated strings are summed).
+template <typename T>
+__global__ void frame_init_kernel(FrameBuffers f, const uint64_t *ox, const uint64_t *oz, const double *oc,
+                                  int nterms) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    unsigned long long len = 0, over = 0;
+    for (int t = 0; t < nterms; ++t) {
+        const uint64_t key = (oz[t] << f.n) | ox[t];
+        const long long j = frame_find(f, key);
+        if (j >= 0) {
+            stc<T>(f.coef, j, ldc<T>(f.coef, j) + oc[t]);
+        } else if ((long long)len < f.cap) {
+            f.keys[len] = key;
+            stc<T>(f.coef, len, oc[t]);
+            frame_insert(f, key, len);
+            ++len;
+        } else {
+            over = 1;
+        }
+    }
+    // the state "after pass -1": slot 2; pass 0 appends into slot 0
+    f.cnt[2] = len;
+    f.cnt[5] = 0;
+    f.cnt[3] = 0;
+    f.cnt[6] = over;
+    *f.updates = 0;
+}
+
+// list length after pass `last` (-1: the observable)
+__device__ __forceinline__ long long frame_len(const FrameBuffers &f, int last) {
+    const int q = frame_slot_of(last);
+    const long long t = (long long)(f.cnt[q] + f.cnt[3 + q]);
+    return t < f.cap ? t : f.cap;
+}
+
+// One pass: its Clifford gates (already in the frame) and its rotation.
+// Counters rotate over three slots, so no workgroup waits for another: the
+// length entering pass `pass` is L + D of the previous slot (stable during
+// this pass), this pass records it in its own slot and counts its children
+// there, and clears the next slot for the pass after.
+template <typename T>
+__global__ __launch_bounds__(SP_BLOCK) void frame_pass_kernel(FrameBuffers f, FramePassDesc p,
+                                                             const double *__restrict__ theta, int pass) {
+#pragma clang fp contract(off)
+    __shared__ int wsum[SP_BLOCK / 64];
+    __shared__ unsigned long long tbase;
+    const int q = frame_slot_of(pass), qprev = frame_slot_of(pass - 1), qnext = frame_slot_of(pass + 1);
+    const long long T0 = frame_len(f, pass - 1);  // list length entering the pass
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *f.updates += (unsigned long long)T0 * (unsigned long long)p.ngates;
+        f.cnt[q] = (unsigned long long)T0;
+        f.cnt[3 + qnext] = 0;
+        if (f.cnt[qprev] + f.cnt[3 + qprev] > (unsigned long long)f.cap) f.cnt[6] = 1;
+    }
+    const int n = f.n, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (p.rot_param < 0) return;
+    double sn, cs;
+    sincos(theta[p.rot_param], &sn, &cs);
+    const double ssn = p.sign > 0 ? sn : -sn;
+    const uint64_t lo = (1ull << n) - 1ull;
+    const uint64_t xp = p.pmask & lo, zp = p.pmask >> n;
+    const long long L = live_tiles(T0);
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        // all items' keys, then the first probe of every anticommuting item,
+        // issued together: the lookups are random accesses, so they are
+        // kept in flight side by side rather than one by one
+        uint64_t key[SP_ITEMS], slot[SP_ITEMS], kc[SP_ITEMS];
+        FrameSlot e[SP_ITEMS];
+        double vc[SP_ITEMS];
+        unsigned anti = 0, kids = 0;
+#pragma unroll
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            const long long i = t * SP_TILE + it * SP_BLOCK + threadIdx.x;
+            key[it] = i < T0 ? f.keys[i] : 0;
+            const bool a = i < T0 && ((__popcll((key[it] & lo) & zp) + __popcll((key[it] >> n) & xp)) & 1);
+            anti |= (unsigned)a << it;
+            slot[it] = frame_home(key[it] ^ p.pmask, f.slot_bits);
+        }
+#pragma unroll
+        for (int it = 0; it < SP_ITEMS; ++it)
+            if ((anti >> it) & 1u) e[it] = frame_slot(f, slot[it]);
+#pragma unroll
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            kc[it] = 0;
+            vc[it] = 0.0;
+            if (!((anti >> it) & 1u)) continue;
+            const long long i = t * SP_TILE + it * SP_BLOCK + threadIdx.x;
+            const uint64_t K = key[it] ^ p.pmask;
+            const long long j = frame_resolve(f, K, slot[it], e[it]);
+            const double cS = ldc<T>(f.coef, i);
+            if (j < 0) {
+                stc<T>(f.coef, i, cS * cs);
+                kids |= 1u << it;
+                kc[it] = K;
+                vc[it] = cS * (frame_child_sign(key[it], p.pmask, p.a, n) * ssn);
+            } else if (key[it] < K) {
+                // both present: S's child lands on K and K's on S
+                const double cK = ldc<T>(f.coef, j);
+                const double gS = frame_child_sign(key[it], p.pmask, p.a, n) * ssn;
+                const double gK = frame_child_sign(K, p.pmask, p.a, n) * ssn;
+                stc<T>(f.coef, i, frame_merge2<T>(cS * cs, cK * gK));
+                stc<T>(f.coef, j, frame_merge2<T>(cK * cs, cS * gS));
+            }
+        }
+        // the tile's children: one counter update per tile, positions from
+        // a workgroup scan of the per-thread counts
+        const int mine = __popc(kids);
+        int incl = mine;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int total = 0;
+            for (int u = 0; u < SP_BLOCK / 64; ++u) total += wsum[u];
+            tbase = total ? atomicAdd(f.cnt + 3 + q, (unsigned long long)total) : 0ull;
+        }
+        __syncthreads();
+        int woff = 0;
+        for (int u = 0; u < w; ++u) woff += wsum[u];
+        unsigned long long pos = (unsigned long long)T0 + tbase + (unsigned long long)(woff + incl - mine);
+#pragma unroll
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            if (!((kids >> it) & 1u)) continue;
+            if ((long long)pos < f.cap) {
+                f.keys[pos] = kc[it];
+                stc<T>(f.coef, (long long)pos, vc[it]);
+                frame_insert(f, kc[it], pos);
+            }
+            ++pos;
+        }
+        __syncthreads();  // wsum and tbase are reused by the next tile
+    }
+}
+
+// Strings whose actual form is made of I and Z only: the x part of the
+// actual string is linear in the key (xrows), so the others are skipped at
+// the cost of n parities; the kept ones replay every Clifford for their
+// actual z and sign.
+template <typename T>
+__global__ __launch_bounds__(SP_BLOCK) void frame_x0_kernel(FrameBuffers f, const uint64_t *__restrict__ xrows,
+                                                           const uint32_t *__restrict__ codes, int ncodes, int npasses,
+                                                           uint64_t *__restrict__ ox, uint64_t *__restrict__ oz, void *oc,
+                                                           long long *__restrict__ ocount) {
+    __shared__ uint64_t rows[64];
+    const int n = f.n, lane = threadIdx.x & 63;
+    if (threadIdx.x < n) rows[threadIdx.x] = xrows[threadIdx.x];
+    __syncthreads();
+    const long long T0 = frame_len(f, npasses - 1);
+    const int ql = frame_slot_of(npasses - 1);
+    const uint64_t lo = (1ull << n) - 1ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ocount[1] = (f.cnt[6] || f.cnt[ql] + f.cnt[3 + ql] > (unsigned long long)f.cap) ? 1 : 0;
+    const long long L = live_tiles(T0);
+    for (long long t = blockIdx.x; t < L; t += gridDim.x) {
+        for (int it = 0; it < SP_ITEMS; ++it) {
+            const long long i = t * SP_TILE + it * SP_BLOCK + threadIdx.x;
+            bool keep = false;
+            uint64_t zz = 0;
+            double v = 0.0;
+            if (i < T0) {
+                const uint64_t key = f.keys[i];
+                unsigned odd = 0;
+                for (int j = 0; j < n; ++j) odd |= (unsigned)__popcll(key & rows[j]) & 1u;
+                if (!odd) {
+                    uint64_t x = key & lo, z = key >> n;
+                    unsigned neg = 0;
+                    clifford_apply(x, z, neg, codes, 0, ncodes);
+                    keep = true;
+                    zz = z;
+                    v = ldc<T>(f.coef, i);
+                    if (neg) v = -v;
+                }
+            }
+            const unsigned long long bal = __ballot(keep);
+            if (bal) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd((unsigned long long *)ocount, (unsigned long long)__popcll(bal));
+                base = __shfl(base, 0, 64);
+                if (keep) {
+                    const long long pos = (long long)(base + (unsigned long long)__popcll(bal & ((1ull << lane) - 1ull)));
+                    ox[pos] = 0;
+                    oz[pos] = zz;
+                    stc<T>(oc, pos, v);
+                }
+            }
+        }
+    }
+}
+
+// Every string in its actual form, at its list position.
+template <typename T>
+__global__ __launch_bounds__(SP_BLOCK) void frame_materialize_kernel(FrameBuffers f, const uint32_t *__restrict__ codes,
+                                                                    int ncodes, int npasses, uint64_t *__restrict__ ox,
+                                                                    uint64_t *__restrict__ oz, void *oc,
+                                                                    long long *__restrict__ ocount) {
+    const long long T0 = frame_len(f, npasses - 1);
+    const int ql = frame_slot_of(npasses - 1);
+    const uint64_t lo = (1ull << f.n) - 1ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ocount[0] = T0;
+        ocount[1] = (f.cnt[6] || f.cnt[ql] + f.cnt[3 + ql] > (unsigned long long)f.cap) ? 1 : 0;
+    }
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < T0; i += (long long)gridDim.x * blockDim.x) {
+        const uint64_t key = f.keys[i];
+        uint64_t x = key & lo, z = key >> f.n;
+        unsigned neg = 0;
+        clifford_apply(x, z, neg, codes, 0, ncodes);
+        ox[i] = x;
+        oz[i] = z;
+        const double v = ldc<T>(f.coef, i);
+        stc<T>(oc, i, neg ? -v : v);
+    }
+}
+
+__global__ void zero_ll_kernel(long long *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
 // ------------------------------------------------------------ launchers
 // grid of a tile kernel: the capacity's tiles, at most SP_GRID workgroups
 static int grid_for(const SparseBuffers &b) {
@@ -687,6 +989,59 @@ hipError_t launch_sparse_readout(SparseBuffers &b, int dtype_bytes, double *part
         hipLaunchKernelGGL(sp_readout_partial_kernel<float>, dim3(RO_BLOCKS), dim3(256), 0, s, b.x, b.c, b.count,
                            partials);
     hipLaunchKernelGGL(sp_readout_final_kernel, dim3(1), dim3(64), 0, s, partials, b.count, out);
+    return hipGetLastError();
+}
+
+static int frame_grid(const FrameBuffers &f) {
+    const long long tiles = (f.cap + SP_TILE - 1) / SP_TILE;
+    return (int)std::max<long long>(1, std::min<long long>(tiles, SP_GRID));
+}
+
+hipError_t launch_frame_init(FrameBuffers &f, int dtype_bytes, const uint64_t *x, const uint64_t *z, const double *c,
+                             int nterms, hipStream_t s) {
+    const long long blocks = std::min<long long>((f.slots + 255) / 256, 8192);
+    hipLaunchKernelGGL(frame_clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, f.index, (long long)f.slots);
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(frame_init_kernel<double>, dim3(1), dim3(64), 0, s, f, x, z, c, nterms);
+    else
+        hipLaunchKernelGGL(frame_init_kernel<float>, dim3(1), dim3(64), 0, s, f, x, z, c, nterms);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_pass(FrameBuffers &f, int dtype_bytes, const FramePassDesc &p, const double *theta, int pass,
+                             hipStream_t s) {
+    // a pass without rotation only counts its gates: one workgroup
+    const int g = p.rot_param >= 0 ? frame_grid(f) : 1;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(frame_pass_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, f, p, theta, pass);
+    else
+        hipLaunchKernelGGL(frame_pass_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, f, p, theta, pass);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_x0(FrameBuffers &f, int dtype_bytes, const uint64_t *xrows, const uint32_t *codes, int ncodes,
+                           int npasses, SparseBuffers &out, hipStream_t s) {
+    hipLaunchKernelGGL(zero_ll_kernel, dim3(1), dim3(64), 0, s, out.count, 8);
+    const int g = frame_grid(f);
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(frame_x0_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, f, xrows, codes, ncodes, npasses,
+                           out.x, out.z, out.c, out.count);
+    else
+        hipLaunchKernelGGL(frame_x0_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, f, xrows, codes, ncodes, npasses,
+                           out.x, out.z, out.c, out.count);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_materialize(FrameBuffers &f, int dtype_bytes, const uint32_t *codes, int ncodes,
+                                    int npasses, SparseBuffers &out, hipStream_t s) {
+    hipLaunchKernelGGL(zero_ll_kernel, dim3(1), dim3(64), 0, s, out.count, 8);
+    const int g = frame_grid(f) * SP_ITEMS;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(frame_materialize_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, f, codes, ncodes, npasses,
+                           out.x, out.z, out.c, out.count);
+    else
+        hipLaunchKernelGGL(frame_materialize_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, f, codes, ncodes, npasses,
+                           out.x, out.z, out.c, out.count);
     return hipGetLastError();
 }
 
