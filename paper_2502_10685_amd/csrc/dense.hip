@@ -102,6 +102,14 @@ __device__ long long block_sum_i(long long v, long long *red) {
     return tot;
 }
 
+// One row of a U1 map, m0 cx + m1 cy + m2 cz, with its rounding points fixed:
+// a product, then two fused multiply-adds.  Every kernel applies maps through
+// it, so all of them round alike whatever the surrounding code would let the
+// compiler contract (a negation folded in from a CX, say).
+__device__ __forceinline__ double map_row(double m0, double m1, double m2, double cx, double cy, double cz) {
+    return __builtin_fma(m2, cz, __builtin_fma(m1, cy, m0 * cx));
+}
+
 // ----------------------------------------------------------------- U1 op
 // Quad u of digit a: the slots base + d * 4^a, d = 0..3, with base the index
 // u with a zero digit inserted at position a.  K (tile digits) and BLOCK are
@@ -137,9 +145,9 @@ __device__ __forceinline__ int u1_apply(T *lc, uint8_t *lp, int a, const double 
     }
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
-        lc[iX[j]] = (T)(m00 * cx[j] + m01 * cy[j] + m02 * cz[j]);
-        lc[iY[j]] = (T)(m10 * cx[j] + m11 * cy[j] + m12 * cz[j]);
-        lc[iZ[j]] = (T)(m20 * cx[j] + m21 * cy[j] + m22 * cz[j]);
+        lc[iX[j]] = (T)map_row(m00, m01, m02, cx[j], cy[j], cz[j]);
+        lc[iY[j]] = (T)map_row(m10, m11, m12, cx[j], cy[j], cz[j]);
+        lc[iZ[j]] = (T)map_row(m20, m21, m22, cx[j], cy[j], cz[j]);
     }
     int delta = 0;
     if (TRACK) {
@@ -310,9 +318,9 @@ template <bool LO, int Q>
 __device__ __forceinline__ void u1_quad(double *v, const double (&m)[9]) {
     constexpr int iX = LO ? 1 + 4 * Q : Q + 4, iZ = LO ? 2 + 4 * Q : Q + 8, iY = LO ? 3 + 4 * Q : Q + 12;
     const double cx = v[iX], cy = v[iY], cz = v[iZ];
-    v[iX] = m[0] * cx + m[1] * cy + m[2] * cz;
-    v[iY] = m[3] * cx + m[4] * cy + m[5] * cz;
-    v[iZ] = m[6] * cx + m[7] * cy + m[8] * cz;
+    v[iX] = map_row(m[0], m[1], m[2], cx, cy, cz);
+    v[iY] = map_row(m[3], m[4], m[5], cx, cy, cz);
+    v[iZ] = map_row(m[6], m[7], m[8], cx, cy, cz);
 }
 
 // U1 (3x3 map M over X, Y, Z) on one digit of a 16-register block; LO: the
@@ -418,13 +426,35 @@ constexpr LaneOrder lane_order() {
     return o;
 }
 
+// The eight common GROUP shapes (see the planner's group_shape): the CX,
+// then the U1 ops in order, with maps m1 and m2 of the first and second U1.
+template <bool CTRL_LO, int CODE>
+__device__ __forceinline__ void shape_apply(double *v, const double (&m1)[9], const double (&m2)[9]) {
+    cx_regs<CTRL_LO>(v);
+    if constexpr (CODE == 0) {
+        u1_regs_m<true>(v, m1);
+    } else if constexpr (CODE == 1) {
+        u1_regs_m<false>(v, m1);
+    } else if constexpr (CODE == 2) {
+        u1_regs_m<true>(v, m1);
+        u1_regs_m<false>(v, m2);
+    } else {
+        u1_regs_m<false>(v, m1);
+        u1_regs_m<true>(v, m2);
+    }
+}
+
 // A GROUP of cnt ops on digits A < B: each thread owns whole 16-slot blocks
 // (all letters of the two digits), applies every member op in registers and
 // writes the block back once.  Compiled per digit pair, so the sixteen
-// letter offsets are constants.
+// letter offsets are constants.  A group of one of the eight common shapes
+// (shape != 0) runs as straight-line code: the CX renames registers instead
+// of moving them, both maps are loaded at once, and each shape writes the
+// block back from its own registers; the same operations in the same order
+// as the general member loop, so the same results.
 template <typename T, int K, int BLOCK, int A, int B>
 __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, int cnt, int tid, const DOp *gops,
-                                            const double *gmaps) {
+                                            const double *gmaps, int shape) {
     constexpr int NG = 1 << (2 * (K - 2));
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
     constexpr LaneOrder lo = lane_order<K, A, B>();
@@ -445,11 +475,46 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
         // member.  Only when every lane of the wave takes part (NG >= 64);
         // smaller tiles read each member's word on its own.
         const int lane = tid & 63;
-        uint32_t wl = 0;
-        if constexpr (NG >= 64) wl = reinterpret_cast<const uint32_t *>(&ops[first + (lane < cnt ? lane : 0)])[0];
+        uint32_t wl = 0, ml = 0;  // word 0 and map index of member `lane`
+        if constexpr (NG >= 64) {
+            const uint32_t *ow = reinterpret_cast<const uint32_t *>(&ops[first + (lane < cnt ? lane : 0)]);
+            wl = ow[0];
+            ml = ow[2];
+        }
         double v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))];
+        if constexpr (NG >= 64) {
+            if (shape != 0) {
+                typedef const __attribute__((address_space(4))) double *CD;
+                const CD s1 = (CD)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, 1);
+                const CD s2 = (CD)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, cnt > 2 ? 2 : 1);
+                double m1[9], m2[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    m1[q] = s1[q];
+                    m2[q] = s2[q];
+                }
+#define PP_SHAPE_CASE(S_, LO_, CODE_)                                                                          \
+    case S_:                                                                                                   \
+        shape_apply<LO_, CODE_>(v, m1, m2);                                                                    \
+        _Pragma("unroll") for (int e = 0; e < 16; ++e) lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))] = \
+            (T)v[e];                                                                                           \
+        continue;
+                switch (shape) {
+                    PP_SHAPE_CASE(1, true, 0)
+                    PP_SHAPE_CASE(2, true, 1)
+                    PP_SHAPE_CASE(3, true, 2)
+                    PP_SHAPE_CASE(4, true, 3)
+                    PP_SHAPE_CASE(5, false, 0)
+                    PP_SHAPE_CASE(6, false, 1)
+                    PP_SHAPE_CASE(7, false, 2)
+                    PP_SHAPE_CASE(8, false, 3)
+                default: break;
+                }
+#undef PP_SHAPE_CASE
+            }
+        }
 #pragma unroll 1
         for (int t = 0; t < cnt; ++t) {
             const uint32_t w0 = NG >= 64
@@ -465,7 +530,10 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
                 // lets the 6-qubit streaming kernel run four waves per SIMD
                 typedef const __attribute__((address_space(4))) uint32_t *CW;
                 typedef const __attribute__((address_space(4))) double *CD;
-                const uint32_t mi = ((CW)(gops + first + t))[2];
+                // the map index from the lane-indexed op words (no dependent
+                // scalar load before the map's own)
+                const uint32_t mi = NG >= 64 ? (uint32_t)__builtin_amdgcn_readlane(ml, t)
+                                             : ((CW)(gops + first + t))[2];
                 const CD src = (CD)gmaps + 9ull * mi;
                 double m[9];
 #pragma unroll
@@ -484,10 +552,10 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
 
 template <typename T, int K, int BLOCK>
 __device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, int first, int cnt, int tid,
-                                            const DOp *gops, const double *gmaps) {
-#define PP_GROUP_CASE(A_, B_)                                                                                \
-    case (A_) * 8 + (B_):                                                                                   \
-        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, first, cnt, tid, gops, gmaps); \
+                                            const DOp *gops, const double *gmaps, int shape) {
+#define PP_GROUP_CASE(A_, B_)                                                                                       \
+    case (A_) * 8 + (B_):                                                                                          \
+        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, first, cnt, tid, gops, gmaps, shape); \
         return;
     switch (a * 8 + b) {
         PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
@@ -541,7 +609,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
             if (kind == DOP_GROUP) {
                 if (i + 1 + ngates > cn) break;  // reload the chunk from this header
                 if constexpr (K >= 2)
-                    group_apply<T, K, BLOCK>(lc, a, b, oc->ops, i + 1, ngates, tid, gops, gmaps);
+                    group_apply<T, K, BLOCK>(lc, a, b, oc->ops, i + 1, ngates, tid, gops, gmaps, (int)perm);
                 i += 1 + ngates;
             } else if (!TRACK && K >= 2 && K <= 7) {
                 // untracked U1 or CX alone: a group sweep of one op over its
@@ -550,7 +618,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
                 const int other = kind == DOP_U1 ? (a == 0 ? 1 : a - 1) : b;
                 if constexpr (K >= 2)
                     group_apply<T, K, BLOCK>(lc, a < other ? a : other, a < other ? other : a, oc->ops, i, 1, tid, gops,
-                                             gmaps);
+                                             gmaps, 0);
                 ++i;
             } else if (kind == DOP_U1) {
                 const int delta = u1_apply<T, TRACK, K, BLOCK>(lc, lp, a, oc->maps[i], smask, tid);
@@ -1007,9 +1075,9 @@ __device__ __forceinline__ void reg_u1(double (&v)[64], const double *__restrict
     for (int e = 0; e < 64; ++e) {
         if ((e >> (2 * P)) & 3) continue;
         const double cx = v[e + S], cz = v[e + 2 * S], cy = v[e + 3 * S];
-        v[e + S] = m00 * cx + m01 * cy + m02 * cz;
-        v[e + 3 * S] = m10 * cx + m11 * cy + m12 * cz;
-        v[e + 2 * S] = m20 * cx + m21 * cy + m22 * cz;
+        v[e + S] = map_row(m00, m01, m02, cx, cy, cz);
+        v[e + 3 * S] = map_row(m10, m11, m12, cx, cy, cz);
+        v[e + 2 * S] = map_row(m20, m21, m22, cx, cy, cz);
     }
 }
 

@@ -59,6 +59,25 @@ namespace {
 
 unsigned op_digits(const DOp &d) { return d.kind == DOP_CX ? (1u << d.a) | (1u << d.b) : (1u << d.a); }
 
+}  // namespace
+
+int group_shape(const DOp *m, int count, int lo) {
+    if (count < 2 || count > 3 || m[0].kind != DOP_CX) return 0;
+    const int dir = m[0].a == lo ? 0 : 1;
+    for (int j = 1; j < count; ++j)
+        if (m[j].kind != DOP_U1) return 0;
+    int code;
+    if (count == 2) {
+        code = m[1].a == lo ? 0 : 1;
+    } else {
+        if ((m[1].a == lo) == (m[2].a == lo)) return 0;
+        code = m[1].a == lo ? 2 : 3;
+    }
+    return 1 + 4 * dir + code;
+}
+
+namespace {
+
 // Regroups a run of ops: repeatedly takes the first remaining op and every
 // later op whose digits stay within one pair of digits and that does not
 // share a digit with an op it would move past (ops on disjoint digits
@@ -102,8 +121,11 @@ std::vector<DOp> group_ops(const std::vector<DOp> &in, int k) {
         h.a = (uint8_t)__builtin_ctz(pair);
         h.b = (uint8_t)(31 - __builtin_clz(pair));
         h.ngates = (uint8_t)mem.size();
+        std::vector<DOp> body;
+        for (size_t j : mem) body.push_back(in[j]);
+        h.perm = (uint16_t)group_shape(body.data(), (int)body.size(), h.a);
         out.push_back(h);
-        for (size_t j : mem) out.push_back(in[j]);
+        out.insert(out.end(), body.begin(), body.end());
     }
     return out;
 }
@@ -486,6 +508,7 @@ std::string plan_check(const DensePlan &P, int n) {
                     if (m.kind == DOP_CX && ((m.b != d.a && m.b != d.b) || m.a == m.b)) return "GROUP CX outside its pair";
                     if (m.kind == DOP_U1 && m.map >= (uint32_t)P.nmaps()) return "map index out of range";
                 }
+                if (d.perm != (uint16_t)group_shape(&P.ops[(size_t)i + 1], d.ngates, d.a)) return "GROUP shape tag";
                 i += d.ngates;
                 continue;
             }

@@ -52,6 +52,13 @@ struct SparsePlan {
 // contain the lowest `low` qubits.
 DensePlan plan_dense(const GateList &g, int k, int low, bool compose, bool reorder);
 constexpr int kMaxGroupOps = 16;
+
+// Shape of a GROUP (stored in its header's perm field; 0 = general): a CX
+// whose control is the lower (dir 0) or higher (dir 1) digit of the pair,
+// then U1 ops on digit sequence code 0 "lower", 1 "higher", 2 "lower,
+// higher", 3 "higher, lower": shape = 1 + 4 dir + code.  These eight cover
+// most groups of random circuits; the kernels run them as straight-line code.
+int group_shape(const DOp *members, int count, int lo);
 // Tile size of the register-tile kernel: its passes are ordered into SEG
 // segments (see segment_ops in plan.cpp).
 constexpr int kSegTileDigits = 6;
