@@ -449,6 +449,8 @@ def cpu_baseline(circs, updates, checks):
     errs["batch_fp64_max_abs_vs_statevector"] = float(np.max(np.abs(checks["batch_f64"] - sv_batch)))
     if checks.get("batch_f32") is not None:
         errs["batch_fp32_max_abs_vs_statevector"] = float(np.max(np.abs(checks["batch_f32"] - sv_batch)))
+    if checks.get("batch_graph_f64") is not None:
+        errs["batch_graph_fp64_max_abs_vs_statevector"] = float(np.max(np.abs(checks["batch_graph_f64"] - sv_batch)))
     if checks.get("served"):
         sv_served = {}
         for (kind, key), r in zip(slots, cres):
@@ -481,6 +483,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sort-merge engine leg")
     ap.add_argument("--no-density", action="store_true", help="skip the density-matrix (toDM) leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed batch leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
                     help="time the tuning candidates on this device first (defaults are MI355X measurements)")
@@ -599,6 +602,31 @@ def main():
     if tuned is not None:
         res["autotune"] = {"tile_kernel": tuned["tile_kernel"], "tile_qubits": tuned["tile_qubits"],
                            "resident_block": tuned["resident_block"], "seconds": round(tuned["seconds"], 1)}
+
+    if not args.no_graph and len(objs) > 1:
+        # the same step captured once as a hipGraph and replayed (theta is
+        # read from device memory at replay); its outputs must equal the
+        # eager step's bit for bit
+        for o in objs:
+            o.set_option(L.PP_OPT_USE_GRAPH, 1)
+        outg = torch.empty_like(out)
+
+        def gstep():
+            api.evaluate_batch(objs, outg)
+        gstep()
+        torch.cuda.synchronize()
+        gs, glat = timed_steps(gstep, args.steps, torch)
+        gv = outg.cpu().numpy()
+        res["batch_graph"] = {
+            "ms_per_step": gs / args.steps * 1e3, "value": u_step * args.steps / gs,
+            "speedup_vs_eager": (total_s / gs), "bitwise_equal_to_eager": bool(
+                np.array_equal(gv.view(np.uint64), gpu_vals.view(np.uint64))),
+            "step_latency_ms": {"p50": float(np.percentile(glat, 50) * 1e3),
+                                "p99": float(np.percentile(glat, 99) * 1e3)}}
+        checks["batch_graph_f64"] = gv
+        for o in objs:
+            o.set_option(L.PP_OPT_USE_GRAPH, 0)
+        log(f"graph-replayed batch: {gs / args.steps * 1e3:.2f} ms/step")
 
     if not args.no_plain and len(objs) > 1:
         def plain():

@@ -92,10 +92,15 @@ typedef enum pp_option {
                                hold 2x this */
     PP_OPT_USE_GRAPH = 3,   /* 1: replay a captured hipGraph for pp_evaluate
                                (tiled DENSE, and SPARSE: its whole pass and
-                               merge sequence, which needs no host sync) and
-                               for pp_gradient (the whole Heisenberg + adjoint
-                               sweep, a training step's launch sequence);
-                               theta is read from device memory at replay */
+                               merge sequence, which needs no host sync), for
+                               pp_gradient (the whole Heisenberg + adjoint
+                               sweep, a training step's launch sequence) and
+                               for pp_evaluate_batch when every circuit of the
+                               batch sets it (the whole step: start weights,
+                               maps, LDS-resident circuits, every tile pass
+                               and the readouts, captured once per set of
+                               circuits and output array); theta is read
+                               from device memory at replay */
     PP_OPT_BLOCK = 4,       /* threads per workgroup (64..1024), 0 = default */
     PP_OPT_SPARSE_FRAME = 5 /* SPARSE, exact runs with n <= 31: 1 (default)
                                propagates in the Clifford frame (Clifford
@@ -242,7 +247,11 @@ PP_API pp_status pp_evaluate(pp_circuit *c, void *stream, double *d_expval);
  * multi-circuit tiled passes.  d_expvals: caller-owned device array of
  * `count` doubles, in input order.  Each circuit's result is bit-identical
  * to its own pp_evaluate.  PP_ERR_INVALID if a circuit appears twice (the
- * launches would update its one weight array from two places). */
+ * launches would update its one weight array from two places).  When every
+ * circuit sets PP_OPT_USE_GRAPH (and all are untracked DENSE), the step is
+ * captured as one hipGraph the first time this set of circuits meets this
+ * output array, and replayed afterwards (same results bit for bit); the
+ * capture is dropped when the set, a schedule or the array changes. */
 PP_API pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, void *stream, double *d_expvals);
 
 /* Parameter sweep (the 2m parameter-shift evaluations of Sec. I, a scan

@@ -1582,8 +1582,64 @@ struct BatchCache {
     int io_off = -1, io_max_n = 0;  // start/readout descriptors of the tiled circuits
     std::vector<int> tiled;        // indices of tiled circuits
     std::vector<int> single;       // indices evaluated one by one
+    // the whole step captured once (every circuit sets PP_OPT_USE_GRAPH)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 BatchCache g_batch;
+
+void free_batch_graph(BatchCache &B) {
+    if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
+    if (B.graph) (void)hipGraphDestroy(B.graph);
+    B.gexec = nullptr;
+    B.graph = nullptr;
+}
+
+// The device work of one batch step on stream s: start weights, composed
+// maps, LDS-resident circuits on the second stream, every tile pass, then
+// the readouts.  It reads theta and writes the outputs through device
+// pointers only, with no host synchronization, so it can be captured.
+pp_status enqueue_batch_body(BatchCache &B, int dbytes, hipStream_t s) {
+    unsigned char *base = (unsigned char *)B.dbuf;
+    if (B.io_off >= 0) {
+        ProfScope ps(PC_INIT, s);
+        HIPCHK(pp::launch_dense_init_many((const pp::DenseIODesc *)(base + B.io_off), (int)B.tiled.size(),
+                                          B.io_max_n, dbytes, s));
+    }
+    bool forked = false;
+    TileSpan span;  // the tile passes come last in the list, all on s
+    for (const auto &L : B.launches) {
+        if (L.kind == 1 && !forked) {  // after the maps are composed
+            HIPCHK(hipEventRecord(B.fork, s));
+            HIPCHK(hipStreamWaitEvent(B.aux, B.fork, 0));
+            forked = true;
+        }
+        if (L.kind == 2) {
+            span.begin(s);
+            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.tg, L.group_n, dbytes, false, s));
+            span.count();
+            continue;
+        }
+        span.end();
+        hipStream_t ls = L.kind == 1 ? B.aux : s;
+        ProfScope ps(L.kind == 0 ? PC_COMPOSE : PC_RES, ls);
+        if (L.kind == 0)
+            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, ls, L.nblocks));
+        else
+            HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, ls));
+    }
+    span.end();
+    if (forked) {
+        HIPCHK(hipEventRecord(B.join, B.aux));
+        HIPCHK(hipStreamWaitEvent(s, B.join, 0));
+    }
+    if (B.io_off >= 0) {
+        ProfScope ps(PC_READOUT, s);
+        HIPCHK(pp::launch_dense_readout_many((const pp::DenseIODesc *)(base + B.io_off), (int)B.tiled.size(), dbytes,
+                                             s));
+    }
+    return PP_OK;
+}
 
 }  // namespace
 
@@ -1616,6 +1672,7 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
     for (int64_t i = 0; hit && i < count; ++i) hit = B.key[i] == cs[i] && B.gens[i] == cs[i]->plan_gen;
     if (!hit) {
         if (B.done) HIPCHK(hipEventSynchronize(B.done));
+        free_batch_graph(B);  // it holds the old descriptors
         B.key.assign(cs, cs + count);
         B.gens.resize(count);
         for (int64_t i = 0; i < count; ++i) B.gens[i] = cs[i]->plan_gen;
@@ -1735,13 +1792,6 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
             if (r != PP_OK) return r;
         }
     }
-    unsigned char *base = (unsigned char *)B.dbuf;
-    // tiled circuits start from their observables (one launch for all)
-    if (B.io_off >= 0) {
-        ProfScope ps(PC_INIT, s);
-        HIPCHK(pp::launch_dense_init_many((const pp::DenseIODesc *)(base + B.io_off), (int)B.tiled.size(),
-                                          B.io_max_n, dbytes, s));
-    }
     bool any_res = false;
     for (const auto &L : B.launches) any_res = any_res || L.kind == 1;
     if (any_res && !B.aux) {
@@ -1749,37 +1799,38 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         HIPCHK(hipEventCreateWithFlags(&B.fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&B.join, hipEventDisableTiming));
     }
-    bool forked = false;
-    TileSpan span;  // the tile passes come last in the list, all on s
-    for (const auto &L : B.launches) {
-        if (L.kind == 1 && !forked) {  // after the maps are composed
-            HIPCHK(hipEventRecord(B.fork, s));
-            HIPCHK(hipStreamWaitEvent(B.aux, B.fork, 0));
-            forked = true;
+    bool graph = B.single.empty();
+    for (int64_t i = 0; graph && i < count; ++i) graph = cs[i]->use_graph != 0;
+    if (graph) {
+        if (!B.gexec) {
+            hipStream_t cap;
+            HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                g_prof.capturing++;
+                r = enqueue_batch_body(B, dbytes, cap);
+                g_prof.capturing--;
+                hipGraph_t gr = nullptr;
+                hipError_t e2 = hipStreamEndCapture(cap, &gr);
+                if (r == PP_OK && e2 == hipSuccess) {
+                    B.graph = gr;
+                    e2 = hipGraphInstantiate(&B.gexec, gr, nullptr, nullptr, 0);
+                } else if (gr) {
+                    (void)hipGraphDestroy(gr);
+                }
+                if (e2 != hipSuccess && r == PP_OK) r = fail(PP_ERR_DEVICE, "batch graph capture failed");
+            } else {
+                r = fail(PP_ERR_DEVICE, "hipStreamBeginCapture failed");
+            }
+            (void)hipStreamDestroy(cap);
+            if (r != PP_OK) {
+                free_batch_graph(B);
+                return r;
+            }
         }
-        if (L.kind == 2) {
-            span.begin(s);
-            HIPCHK(pp::launch_tile_pass((const pp::TilePassDesc *)(base + L.off), L.tg, L.group_n, dbytes, false, s));
-            span.count();
-            continue;
-        }
-        span.end();
-        hipStream_t ls = L.kind == 1 ? B.aux : s;
-        ProfScope ps(L.kind == 0 ? PC_COMPOSE : PC_RES, ls);
-        if (L.kind == 0)
-            HIPCHK(pp::launch_compose((const pp::ComposeDesc *)(base + L.off), L.nd, ls, L.nblocks));
-        else
-            HIPCHK(pp::launch_resident((const pp::ResidentDesc *)(base + L.off), L.nd, L.group_n, dbytes, false, ls));
-    }
-    span.end();
-    if (forked) {
-        HIPCHK(hipEventRecord(B.join, B.aux));
-        HIPCHK(hipStreamWaitEvent(s, B.join, 0));
-    }
-    if (B.io_off >= 0) {
-        ProfScope ps(PC_READOUT, s);
-        HIPCHK(pp::launch_dense_readout_many((const pp::DenseIODesc *)(base + B.io_off), (int)B.tiled.size(), dbytes,
-                                             s));
+        HIPCHK(hipGraphLaunch(B.gexec, s));
+    } else if ((r = enqueue_batch_body(B, dbytes, s)) != PP_OK) {
+        return r;
     }
     for (int i : B.single)
         if ((r = pp_evaluate(cs[i], stream, d_expvals + i)) != PP_OK) return r;

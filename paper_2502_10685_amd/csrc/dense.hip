@@ -29,12 +29,17 @@ namespace pp {
 
 // Bank swizzle for 8-byte LDS words.  The LDS has 64 four-byte banks and
 // serves a 64-bit read or write per half-wave, so a half-wave is free of
-// conflicts when its 32 slot indices are distinct modulo 32.  The swizzle
-// XORs index bits 0-4 with bits 5-9 and with bits 7-11: it is linear over
-// GF(2), keeps every 32-slot block's set of high bits, and (with the lane
-// order that group_sweep picks per digit pair) lets every digit pair of 5-,
-// 6- and 7-digit tiles be swept without conflicts.
-__host__ __device__ constexpr int sw(int i) { return i ^ ((i >> 5) & 31) ^ ((i >> 7) & 31); }
+// conflicts when its 32 slot indices are distinct modulo 32.  With h the
+// index bits from bit 5 up, the swizzle XORs bits 0-4 with h << 3, h and
+// h >> 2: it is linear over GF(2) and keeps every 32-slot block's set of
+// high bits.  With the lane order group_sweep picks per digit pair, every
+// digit pair of 5-, 6- and 7-digit tiles is swept without conflicts, and in
+// 6-digit tiles so is every pair of digits 0-4 with the lanes drawn from the
+// three other digits below 5 alone.
+__host__ __device__ constexpr int sw(int i) {
+    const int h = i >> 5;
+    return i ^ (((h << 3) ^ h ^ (h >> 2)) & 31);
+}
 
 // sw(base ^ off) = sw(base) ^ sw(off): slot offsets of an op's letters are
 // the same for every lane, so each address costs one XOR with a uniform.
@@ -376,6 +381,7 @@ __device__ __forceinline__ void stage_ops(OpCacheN<CH> *oc, const DOp *ops, cons
 // distinct bank pairs; the other free bits follow in ascending order.
 struct LaneOrder {
     int pos[14];
+    bool conflict_free;  // the first five positions were found
 };
 constexpr int gf2_rank(int *v, int n) {
     int r = 0;
@@ -421,6 +427,7 @@ constexpr LaneOrder lane_order() {
                         for (int k = 0; k < 5; ++k) o.pos[j++] = fr[idx[k]];
                         for (int f = 0; f < nf; ++f)
                             if (f != i0 && f != i1 && f != i2 && f != i3 && f != i4) o.pos[j++] = fr[f];
+                        o.conflict_free = true;
                         return o;
                     }
     return o;
@@ -458,6 +465,7 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
     constexpr int NG = 1 << (2 * (K - 2));
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
     constexpr LaneOrder lo = lane_order<K, A, B>();
+    static_assert(K < 5 || lo.conflict_free, "every digit pair of a 5- to 7-digit tile has a conflict-free lane order");
     if (NG < BLOCK && tid >= NG) return;
 #pragma unroll 1
     for (int j = 0; j < GPT; ++j) {
