@@ -246,18 +246,23 @@ def gradient_leg(api, torch):
 
 
 def sparse_leg(api, torch):
-    """The sort-merge engine past the dense range (n = 20, 4^n slots): a seeded
+    """The SPARSE engine past the dense range (n = 20, 4^n slots): a seeded
     300-gate random circuit (2.66M strings at the end) and the spread circuit
-    (n = 20, RY on 5 qubits: 7,962,624 strings), one evaluation each timed,
-    launched eagerly and replayed as a captured hipGraph."""
+    (n = 20, RY on 5 qubits: 7,962,624 strings).  Each is timed with the
+    Clifford-frame engine (the default for exact runs with n <= 31; eager and
+    replayed as a captured hipGraph) and with the sort-merge engine (the
+    radix sort at the tuned shape of its capacity class); both must leave the
+    same <O> and the same term-update count."""
+    from paper_2502_10685_amd import _lib as L
     from paper_2502_10685_amd import workloads as W
     cases = [("random n=20 m=300 seed 20", W.random_circuit(np.random.default_rng(20), 20, 300, W.obs_z(20, [0, 1]))),
              ("spread n=20 k=5", W.spread_circuit(20, 20, 5))]
     out = []
     for name, wc in cases:
         row = {"workload": name, "gates": wc.m}
-        for graph in (False, True):
+        for frame, graph in ((1, False), (1, True), (0, False)):
             c = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 24, use_graph=graph)
+            c.set_option(L.PP_OPT_SPARSE_FRAME, frame)
             c.evaluate()
             torch.cuda.synchronize()
             reps = 5
@@ -267,14 +272,21 @@ def sparse_leg(api, torch):
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
             st = c.stats()
-            if graph:
+            if frame and graph:
                 row.update({"ms_graph": dt * 1e3, "updates_per_s_graph": st["term_updates"] / dt,
                             "expval_graph": float(ev.item())})
-            else:
-                row.update({"ms": dt * 1e3, "final_terms": int(st["final_terms"]),
+            elif frame:
+                row.update({"engine": "clifford frame", "ms": dt * 1e3, "final_terms": int(st["final_terms"]),
                             "term_updates": int(st["term_updates"]), "passes": int(st["passes"]),
                             "updates_per_s": st["term_updates"] / dt, "overflow": bool(st["overflow"]),
                             "expval": float(ev.item())})
+            else:
+                cls = 2  # capacity 2^24 strings
+                row["sort_merge"] = {
+                    "ms": dt * 1e3, "updates_per_s": st["term_updates"] / dt, "expval": float(ev.item()),
+                    "sort_shape": L.tune_get(L.PP_TUNE_SORT_SHAPE, cls),
+                    "same_updates_as_frame": int(st["term_updates"]) == row["term_updates"],
+                    "expval_abs_diff_vs_frame": abs(float(ev.item()) - row["expval"])}
             c.close()
         out.append(row)
     # truncated propagation past the exact method's reach (approximate; the
@@ -481,14 +493,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
-    ap.add_argument("--no-sparse", action="store_true", help="skip the sort-merge engine leg")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the SPARSE engine leg")
     ap.add_argument("--no-density", action="store_true", help="skip the density-matrix (toDM) leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed batch leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
                     help="time the tuning candidates on this device first (defaults are MI355X measurements)")
     ap.add_argument("--tune", default="",
-                    help="tuning knobs, e.g. 'kernel:6=1,qubits:12=7' (tile kernel variant per k, tile qubits per n)")
+                    help="tuning knobs, e.g. 'kernel:6=1,qubits:12=7,sort:2=3' (tile kernel variant per k, tile "
+                         "qubits per n, radix-sort shape per SPARSE capacity class)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -514,7 +527,8 @@ def main():
     for item in filter(None, args.tune.split(",")):
         what, rest = item.split(":")
         idx, val = rest.split("=")
-        key = {"kernel": L.PP_TUNE_TILE_KERNEL, "qubits": L.PP_TUNE_TILE_QUBITS, "resblock": L.PP_TUNE_RESIDENT_BLOCK}
+        key = {"kernel": L.PP_TUNE_TILE_KERNEL, "qubits": L.PP_TUNE_TILE_QUBITS, "resblock": L.PP_TUNE_RESIDENT_BLOCK,
+               "sort": L.PP_TUNE_SORT_SHAPE}
         L.tune_set(key[what], int(idx), int(val))
 
     tuned = None
@@ -601,7 +615,8 @@ def main():
                        "stay context"}}
     if tuned is not None:
         res["autotune"] = {"tile_kernel": tuned["tile_kernel"], "tile_qubits": tuned["tile_qubits"],
-                           "resident_block": tuned["resident_block"], "seconds": round(tuned["seconds"], 1)}
+                           "resident_block": tuned["resident_block"], "sort_shape": tuned.get("sort_shape"),
+                           "seconds": round(tuned["seconds"], 1)}
 
     if not args.no_graph and len(objs) > 1:
         # the same step captured once as a hipGraph and replayed (theta is

@@ -425,6 +425,16 @@ PP_API void pp_server_destroy(pp_server *s);
  *                        variant 0.
  *   PP_TUNE_RESIDENT_BLOCK: index = n (5..7), value = 256, 512 or 1024
  *                        threads for the LDS-resident kernel (untracked runs).
+ *   PP_TUNE_SORT_SHAPE: index = capacity class of a SPARSE circuit's term
+ *                        buffers (0: up to 2^17 terms, 1: up to 2^21, 2:
+ *                        larger), value = shape of the radix sort that
+ *                        merges equal strings (reduce(), eq. (7)): 0 = 8 key
+ *                        bits per pass, 8 terms per thread (256 threads);
+ *                        1 = 8 bits, 4 terms; 2 = 8 bits, 16 terms; 3 = 7
+ *                        bits, 8 terms (128 threads); 4 = 7 bits, 16 terms;
+ *                        5 = 6 bits, 16 terms (64 threads).  Every shape is
+ *                        a stable sort on the same key: same order, same
+ *                        results.
  * The kernel variants give bit-identical results for a given tile size; k
  * changes how ops are packed and therefore the rounding, so a circuit keeps
  * the k of its schedule.  The resident block size changes the order of the
@@ -432,7 +442,8 @@ PP_API void pp_server_destroy(pp_server *s);
 typedef enum pp_tune_key {
     PP_TUNE_TILE_QUBITS = 0,
     PP_TUNE_TILE_KERNEL = 1,
-    PP_TUNE_RESIDENT_BLOCK = 2
+    PP_TUNE_RESIDENT_BLOCK = 2,
+    PP_TUNE_SORT_SHAPE = 3
 } pp_tune_key;
 PP_API pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value);
 PP_API pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value);

@@ -1,7 +1,9 @@
 """Project autotuner: picks, by timing on the device, the tile-pass kernel
 variant per tile size and the tile size (qubits per LDS tile) per register
-size n, for batched throughput.  Results are cached as JSON keyed by the
-device name and weight dtype, and applied through pp_tune_set.
+size n, for batched throughput, and the radix-sort shape (key bits per pass,
+terms per thread) of the SPARSE engine's merge per term-capacity class.
+Results are cached as JSON keyed by the device name and weight dtype, and
+applied through pp_tune_set.
 
 Probes are seeded random circuits (50% H/S/CX, 50% RX/RY/RZ) evaluated in
 batches large enough to fill the GPU; every candidate gives bit-identical
@@ -20,6 +22,11 @@ from . import _lib as L
 
 VARIANT_NAMES = {0: "workgroup-per-tile", 1: "persistent-prefetch", 2: "wave-per-tile",
                  3: "register-tile", 4: "register-tile-prefetch"}
+# radix-sort shapes of the SPARSE merge: (key bits per pass, terms per thread)
+SORT_SHAPES = {0: (8, 8), 1: (8, 4), 2: (8, 16), 3: (7, 8), 4: (7, 16), 5: (6, 16)}
+# per capacity class: the largest term capacity of the class and a probe
+# circuit (qubits, gates) whose string set grows to a sizeable part of it
+SORT_CLASSES = {0: (1 << 17, 16, 70), 1: (1 << 21, 20, 130), 2: (1 << 23, 20, 200)}
 
 
 def _device_name():
@@ -42,6 +49,8 @@ def apply(table):
         L.tune_set(L.PP_TUNE_TILE_KERNEL, int(k), int(v))
     for n, k in table.get("tile_qubits", {}).items():
         L.tune_set(L.PP_TUNE_TILE_QUBITS, int(n), int(k))
+    for cls, v in table.get("sort_shape", {}).items():
+        L.tune_set(L.PP_TUNE_SORT_SHAPE, int(cls), int(v))
 
 
 def load_cached(dtype="f64", apply_now=True):
@@ -84,10 +93,73 @@ def _count_for(n):
     return max(2, min(64, (1 << 16) // (4 ** (n - 6))))
 
 
-def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None, resident=(5, 6, 7)):
+def _sort_probe(api, cls, dtype, say):
+    """A sort-merge SPARSE circuit of capacity class cls whose strings fill
+    a sizeable part of the capacity (fewer gates until nothing overflows)."""
+    from . import workloads as W
+    cap, n, m = SORT_CLASSES[cls]
+    for _ in range(8):
+        w = W.random_circuit(np.random.default_rng(9300 + cls), n, m, W.obs_z(n, [0, 1]))
+        c = api.Circuit.from_workload(w, dtype=dtype, engine="sparse", max_terms=cap)
+        c.set_option(L.PP_OPT_SPARSE_FRAME, 0)
+        c.evaluate()
+        st = c.stats()
+        if not st["overflow"]:
+            return c, st
+        c.close()
+        m = m * 3 // 4
+    say(f"sort class {cls}: no probe fits the capacity")
+    return None, None
+
+
+def tune_sort(dtype="f64", log=None, reps=3):
+    """Times every radix-sort shape on one sort-merge probe per capacity class
+    and applies the fastest; returns {"sort_shape": {cls: shape}, "timings":
+    ...}.  Every shape must give the same <O> bit for bit."""
+    import torch
+    from . import api
+    say = log or (lambda s: None)
+    res = {"sort_shape": {}, "timings": {}}
+    for cls in SORT_CLASSES:
+        c, st = _sort_probe(api, cls, dtype, say)
+        if c is None:
+            continue
+        best, times, ref = None, {}, None
+        old = L.tune_get(L.PP_TUNE_SORT_SHAPE, cls)
+        for v in SORT_SHAPES:
+            L.tune_set(L.PP_TUNE_SORT_SHAPE, cls, v)
+            ev = c.evaluate()
+            torch.cuda.synchronize()
+            bits = np.float64(ev.item()).view(np.uint64)
+            if ref is None:
+                ref = bits
+            elif bits != ref:
+                L.tune_set(L.PP_TUNE_SORT_SHAPE, cls, old)
+                raise RuntimeError(f"sort shape {v} changed <O> in class {cls}")
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                c.evaluate()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            times[v] = float(np.median(ts))
+            if best is None or times[v] < times[best]:
+                best = v
+        L.tune_set(L.PP_TUNE_SORT_SHAPE, cls, best)
+        res["sort_shape"][str(cls)] = best
+        res["timings"][str(cls)] = {"terms": int(st["final_terms"]),
+                                    **{f"{SORT_SHAPES[v][0]}b{SORT_SHAPES[v][1]}i": t for v, t in times.items()}}
+        say(f"sort shape class {cls} ({st['final_terms']} strings): {SORT_SHAPES[best]} "
+            f"({ {SORT_SHAPES[v]: round(t * 1e3, 2) for v, t in times.items()} } ms)")
+        c.close()
+    return res
+
+
+def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None, resident=(5, 6, 7), sort=True):
     """Times every candidate and returns (and applies, and caches) the table
     {"tile_kernel": {k: variant}, "tile_qubits": {n: k},
-     "resident_block": {n: threads}, "timings": ...}."""
+     "resident_block": {n: threads}, "sort_shape": {class: shape},
+     "timings": ...}."""
     from . import api
     say = log or (lambda s: None)
     table = {"tile_kernel": {}, "tile_qubits": {}, "resident_block": {},
@@ -142,6 +214,11 @@ def tune(sizes=(8, 9, 10, 11, 12), dtype="f64", m=1200, save=True, log=None, res
         table["tile_qubits"][str(n)] = best
         table["timings"]["tile_qubits"][str(n)] = {str(k): t for k, t in times.items()}
         say(f"tile qubits n={n}: k={best} ({ {k: round(t * 1e3, 2) for k, t in times.items()} } ms)")
+    # 3. radix-sort shape of the SPARSE merge per capacity class
+    if sort:
+        srt = tune_sort(dtype, log=log)
+        table["sort_shape"] = srt["sort_shape"]
+        table["timings"]["sort_shape"] = srt["timings"]
     if save:
         p = cache_path(dtype)
         os.makedirs(os.path.dirname(p), exist_ok=True)

@@ -659,7 +659,7 @@ pp_status ensure_state(pp_circuit *c, bool weights = true) {
         HIPCHK(dalloc(&c->sb.count, 8));
         HIPCHK(dalloc(&c->sb.scan, 256));
         HIPCHK(dalloc(&c->sb.updates, 1));
-        HIPCHK(dalloc(&c->sb.hist, (size_t)256 * tiles));
+        HIPCHK(dalloc(&c->sb.hist, (size_t)pp::sort_hist_entries(cap2)));
         HIPCHK(dalloc(&c->sb.tile_flags, (size_t)tiles));
         HIPCHK(dalloc(&c->d_dropped, (size_t)tiles + 1));
         HIPCHK(dalloc(&c->d_partials, 256));
@@ -1421,7 +1421,7 @@ pp_status pp_get_terms(pp_circuit *c, void *stream, int64_t capacity, uint64_t *
         ok = ok && dalloc(&tmp.count, 8) == hipSuccess;
         ok = ok && dalloc(&tmp.scan, 256) == hipSuccess;
         ok = ok && dalloc(&tmp.updates, 1) == hipSuccess;
-        ok = ok && dalloc(&tmp.hist, (size_t)256 * tiles) == hipSuccess;
+        ok = ok && dalloc(&tmp.hist, (size_t)pp::sort_hist_entries(slots)) == hipSuccess;
         ok = ok && dalloc(&tmp.tile_flags, (size_t)std::max<int64_t>(tiles, slots / 4096 + 1)) == hipSuccess;
         unsigned long long *total = c->d_counters + 2;
         if (ok) {
@@ -2951,6 +2951,12 @@ extern "C" pp_status pp_tune_set(pp_tune_key key, int32_t index, int32_t value) 
         pp::set_resident_block(index, value);
         return PP_OK;
     }
+    if (key == PP_TUNE_SORT_SHAPE) {
+        if (index < 0 || index >= pp::kSortClasses || value < 0 || value >= pp::kSortShapeCount)
+            return fail(PP_ERR_INVALID, "sort shape: class 0..2, value 0..5");
+        pp::set_sort_shape(index, value);
+        return PP_OK;
+    }
     return fail(PP_ERR_INVALID, "unknown tuning key");
 }
 
@@ -2966,6 +2972,10 @@ extern "C" pp_status pp_tune_get(pp_tune_key key, int32_t index, int32_t *value)
     }
     if (key == PP_TUNE_RESIDENT_BLOCK && index >= 5 && index <= 7) {
         *value = pp::resident_block(index);
+        return PP_OK;
+    }
+    if (key == PP_TUNE_SORT_SHAPE && index >= 0 && index < pp::kSortClasses) {
+        *value = pp::sort_shape(index);
         return PP_OK;
     }
     return fail(PP_ERR_INVALID, "unknown tuning key or index");

@@ -216,7 +216,7 @@ struct SparseBuffers {
                           // [3] count before a merge, [4] scan total (8 words)
     long long *scan;      // per-workgroup sums of the multi-workgroup scan (256)
     unsigned long long *updates;
-    unsigned int *hist;   // radix histograms
+    unsigned int *hist;   // radix histograms (sort_hist_entries(cap2) entries)
     int *tile_flags;      // decoupled look-back state
     unsigned long long *tile_vals;
     int *ticket;
@@ -225,6 +225,17 @@ struct SparseBuffers {
 };
 hipError_t launch_sparse_init(SparseBuffers &b, int dtype_bytes, const uint64_t *x, const uint64_t *z,
                               const double *c, int nterms, hipStream_t s, double *dropped_total = nullptr);
+// Radix-sort shape of the merge, per capacity class (cap2 up to 2^18, up to
+// 2^22, larger): 0 = 8 key bits per pass and 8 terms per thread (the
+// default), 1 = 8 and 4, 2 = 8 and 16, 3 = 7 and 8, 4 = 7 and 16, 5 = 6 and
+// 16.  All shapes give the same order; the histogram array must hold
+// sort_hist_entries(cap2) words for any of them.
+constexpr int kSortShapeCount = 6;
+constexpr int kSortClasses = 3;
+int sort_shape_class(long long cap2);
+void set_sort_shape(int cls, int shape);
+int sort_shape(int cls);
+long long sort_hist_entries(long long cap2);
 // Truncated propagation (approximate; off when on == 0): a split child with
 // more than max_weight non-identity letters is not written, and a merged
 // string with more letters or with |weight| < eps is dropped.  The absolute

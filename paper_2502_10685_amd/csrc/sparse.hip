@@ -24,8 +24,6 @@ namespace pp {
 constexpr int SP_BLOCK = 256;
 constexpr int SP_ITEMS = 8;
 constexpr int SP_TILE = SP_BLOCK * SP_ITEMS;  // 2048 terms per block
-constexpr int RADIX_BITS = 8;
-constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SP_GRID = 2048;  // cap on the workgroups of a tile kernel
 
 template <typename T>
@@ -132,8 +130,8 @@ __global__ __launch_bounds__(SP_BLOCK) void pass_count_kernel(const uint64_t *__
     }
 }
 
-// Exclusive scan, in place, of a[0, len) with len = mult * (live tiles of
-// count[0]).  SCAN_BLOCKS workgroups each own one contiguous chunk: the first
+// Exclusive scan, in place, of a[0, len) with len = mult * (tiles of `tile`
+// terms that count[0] terms fill).  SCAN_BLOCKS workgroups each own one contiguous chunk: the first
 // kernel sums every chunk, the second adds to each chunk the sums of the
 // chunks before it and scans it; the last workgroup leaves the grand total.
 constexpr int SCAN_BLOCKS = 256;
@@ -156,10 +154,10 @@ __device__ __forceinline__ long long block_sum_1024(long long v, long long *wsum
 
 template <typename V>
 __global__ __launch_bounds__(1024) void scan_reduce_kernel(const V *__restrict__ a, const long long *__restrict__ count,
-                                                          int mult, long long *__restrict__ bsum) {
+                                                          int mult, int tile, long long *__restrict__ bsum) {
     __shared__ long long wsum[16];
     long long lo, hi;
-    scan_chunk(mult * live_tiles(count[0]), lo, hi);
+    scan_chunk(mult * ((count[0] + tile - 1) / tile), lo, hi);
     long long s = 0;
     for (long long i = lo + threadIdx.x; i < hi; i += 1024) s += (long long)a[i];
     s = block_sum_1024(s, wsum);
@@ -168,12 +166,13 @@ __global__ __launch_bounds__(1024) void scan_reduce_kernel(const V *__restrict__
 
 template <typename V>
 __global__ __launch_bounds__(1024) void scan_apply_kernel(V *__restrict__ a, const long long *__restrict__ count, int mult,
-                                                         const long long *__restrict__ bsum, long long *__restrict__ total) {
+                                                         int tile, const long long *__restrict__ bsum,
+                                                         long long *__restrict__ total) {
     __shared__ long long wsum[16];
     __shared__ long long carry;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     long long lo, hi;
-    scan_chunk(mult * live_tiles(count[0]), lo, hi);
+    scan_chunk(mult * ((count[0] + tile - 1) / tile), lo, hi);
     const long long before = block_sum_1024(tid < (int)blockIdx.x ? bsum[tid] : 0, wsum);
     if (tid == 0) carry = before;
     __syncthreads();
@@ -306,79 +305,89 @@ __global__ __launch_bounds__(SP_BLOCK) void trunc_total_kernel(double *__restric
 
 // ---------------------------------------------------------- radix sort
 // Key = (z << n) | x as a 2n-bit integer (canonical order: by z, then x).
+// The sort's shape is a runtime choice (pp_tune_set): BITS key bits per
+// pass with one thread per digit value (2^BITS threads), ITEMS terms per
+// thread, so a tile holds 2^BITS x ITEMS terms.  Every shape is a stable LSD
+// sort on the same key, so every shape gives the same order.
+template <int BITS>
 __device__ __forceinline__ unsigned key_digit(uint64_t x, uint64_t z, int n, int s) {
     uint64_t v;
     if (s >= n) v = z >> (s - n);
-    else if (s + RADIX_BITS <= n) v = x >> s;
+    else if (s + BITS <= n) v = x >> s;
     else v = (x >> s) | (z << (n - s));
-    return (unsigned)(v & (RADIX - 1));
+    return (unsigned)(v & ((1u << BITS) - 1));
 }
 
 // Histograms are digit-major over the live tiles: hist[d * L + tile], so an
-// exclusive scan of hist[0, RADIX * L) gives every (digit, tile) its output
+// exclusive scan of hist[0, 2^BITS * L) gives every (digit, tile) its output
 // position.
-__global__ __launch_bounds__(SP_BLOCK) void sort_hist_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z,
-                                                            const long long *__restrict__ count, int n, int shift,
-                                                            unsigned *__restrict__ hist) {
-    __shared__ unsigned h[RADIX];
+template <int BITS, int ITEMS>
+__global__ __launch_bounds__(1 << BITS) void sort_hist_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z,
+                                                              const long long *__restrict__ count, int n, int shift,
+                                                              unsigned *__restrict__ hist) {
+    constexpr int RX = 1 << BITS, BLOCK = RX, TILE = BLOCK * ITEMS;
+    __shared__ unsigned h[RX];
     const long long T = count[0];
-    const long long L = live_tiles(T);
+    const long long L = (T + TILE - 1) / TILE;
     for (long long t = blockIdx.x; t < L; t += gridDim.x) {
-        for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) h[d] = 0;
+        h[threadIdx.x] = 0;
         __syncthreads();
-        const long long b0 = t * SP_TILE;
-        for (int it = 0; it < SP_ITEMS; ++it) {
-            const long long i = b0 + it * SP_BLOCK + threadIdx.x;
-            if (i < T) atomicAdd(&h[key_digit(x[i], z[i], n, shift)], 1u);
+        const long long b0 = t * TILE;
+        for (int it = 0; it < ITEMS; ++it) {
+            const long long i = b0 + it * BLOCK + threadIdx.x;
+            if (i < T) atomicAdd(&h[key_digit<BITS>(x[i], z[i], n, shift)], 1u);
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) hist[(long long)d * L + t] = h[d];
+        hist[(long long)threadIdx.x * L + t] = h[threadIdx.x];
         __syncthreads();
     }
 }
 
 // Stable scatter of one tile.  Wave w owns the contiguous sub-tile
-// [w*512, (w+1)*512) and walks it in chunks of 64; lanes with equal digits
-// are matched with eight ballots, so the rank of a term is (terms of its
-// digit in earlier waves) + (earlier chunks of its wave) + (lower lanes of
-// its chunk).  Terms are staged in LDS in sorted order and written out so
-// that each digit's run leaves the workgroup contiguously.
-template <typename T>
-__global__ __launch_bounds__(SP_BLOCK) void sort_scatter_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z,
-                                                               const void *c, uint64_t *__restrict__ xo,
-                                                               uint64_t *__restrict__ zo, void *co,
-                                                               const long long *__restrict__ count, int n, int shift,
-                                                               const unsigned *__restrict__ hist) {
-    __shared__ unsigned whist[SP_BLOCK / 64][RADIX];
-    __shared__ unsigned tpre[RADIX];
-    __shared__ unsigned goff[RADIX];
-    __shared__ uint64_t sx[SP_TILE];
-    __shared__ uint64_t sz[SP_TILE];
-    __shared__ T sc[SP_TILE];
+// [w*64*ITEMS, (w+1)*64*ITEMS) and walks it in chunks of 64; lanes with
+// equal digits are matched with BITS ballots, so the rank of a term is
+// (terms of its digit in earlier waves) + (earlier chunks of its wave) +
+// (lower lanes of its chunk).  Terms are staged in LDS in sorted order and
+// written out so that each digit's run leaves the workgroup contiguously.
+template <typename T, int BITS, int ITEMS>
+__global__ __launch_bounds__(1 << BITS) void sort_scatter_kernel(const uint64_t *__restrict__ x,
+                                                                 const uint64_t *__restrict__ z, const void *c,
+                                                                 uint64_t *__restrict__ xo, uint64_t *__restrict__ zo,
+                                                                 void *co, const long long *__restrict__ count, int n,
+                                                                 int shift, const unsigned *__restrict__ hist) {
+    constexpr int RX = 1 << BITS, BLOCK = RX, TILE = BLOCK * ITEMS, WAVES = BLOCK / 64;
+    static_assert(BLOCK >= 64, "at least one full wave");
+    __shared__ unsigned whist[WAVES][RX];
+    __shared__ unsigned tpre[RX];
+    __shared__ unsigned goff[RX];
+    __shared__ uint64_t sx[TILE];
+    __shared__ uint64_t sz[TILE];
+    __shared__ T sc[TILE];
     const long long Tn = count[0];
-    const long long L = live_tiles(Tn);
+    const long long L = (Tn + TILE - 1) / TILE;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     for (long long t = blockIdx.x; t < L; t += gridDim.x) {
-        const long long b0 = t * SP_TILE;
-        for (int d = threadIdx.x; d < RADIX; d += SP_BLOCK) {
-            for (int v = 0; v < SP_BLOCK / 64; ++v) whist[v][d] = 0;
+        const long long b0 = t * TILE;
+        {
+            const int d = threadIdx.x;
+            for (int v = 0; v < WAVES; ++v) whist[v][d] = 0;
             goff[d] = hist[(long long)d * L + t];
         }
         __syncthreads();
 
-        uint64_t rx[SP_ITEMS], rz[SP_ITEMS];
-        T rc[SP_ITEMS];
-        unsigned rd[SP_ITEMS], rr[SP_ITEMS];
-        for (int j = 0; j < SP_ITEMS; ++j) {
-            const long long i = b0 + (long long)w * (SP_ITEMS * 64) + j * 64 + lane;
+        uint64_t rx[ITEMS], rz[ITEMS];
+        T rc[ITEMS];
+        unsigned rd[ITEMS], rr[ITEMS];
+        for (int j = 0; j < ITEMS; ++j) {
+            const long long i = b0 + (long long)w * (ITEMS * 64) + j * 64 + lane;
             const bool live = i < Tn;
             rx[j] = live ? x[i] : 0;
             rz[j] = live ? z[i] : 0;
             rc[j] = live ? ((const T *)c)[i] : (T)0;
-            const unsigned d = key_digit(rx[j], rz[j], n, shift);
+            const unsigned d = key_digit<BITS>(rx[j], rz[j], n, shift);
             unsigned long long peers = __ballot(live);
-            for (int bt = 0; bt < RADIX_BITS; ++bt) {
+            for (int bt = 0; bt < BITS; ++bt) {
                 const unsigned long long bb = __ballot((d >> bt) & 1u);
                 peers &= ((d >> bt) & 1u) ? bb : ~bb;
             }
@@ -387,16 +396,16 @@ __global__ __launch_bounds__(SP_BLOCK) void sort_scatter_kernel(const uint64_t *
             const int rank = __popcll(peers & lt);
             if (live && rank == 0) whist[w][d] = before + (unsigned)__popcll(peers);
             __builtin_amdgcn_wave_barrier();
-            rd[j] = live ? d : RADIX;
+            rd[j] = live ? d : RX;
             rr[j] = before + (unsigned)rank;
         }
         __syncthreads();
         // per digit: exclusive prefix over waves, then an exclusive scan of the
-        // tile's digit totals (thread d owns digit d; SP_BLOCK == RADIX)
+        // tile's digit totals (thread d owns digit d)
         {
             const int d = threadIdx.x;
             unsigned run = 0;
-            for (int v = 0; v < SP_BLOCK / 64; ++v) {
+            for (int v = 0; v < WAVES; ++v) {
                 const unsigned cnt = whist[v][d];
                 whist[v][d] = run;
                 run += cnt;
@@ -414,8 +423,8 @@ __global__ __launch_bounds__(SP_BLOCK) void sort_scatter_kernel(const uint64_t *
             tpre[d] = add + inc - run;
         }
         __syncthreads();
-        for (int j = 0; j < SP_ITEMS; ++j) {
-            if (rd[j] < RADIX) {
+        for (int j = 0; j < ITEMS; ++j) {
+            if (rd[j] < RX) {
                 const unsigned pos = tpre[rd[j]] + whist[w][rd[j]] + rr[j];
                 sx[pos] = rx[j];
                 sz[pos] = rz[j];
@@ -423,9 +432,9 @@ __global__ __launch_bounds__(SP_BLOCK) void sort_scatter_kernel(const uint64_t *
             }
         }
         __syncthreads();
-        const int valid = (int)((Tn - b0) < SP_TILE ? (Tn - b0) : SP_TILE);
-        for (int i = threadIdx.x; i < valid; i += SP_BLOCK) {
-            const unsigned d = key_digit(sx[i], sz[i], n, shift);
+        const int valid = (int)((Tn - b0) < TILE ? (Tn - b0) : TILE);
+        for (int i = threadIdx.x; i < valid; i += BLOCK) {
+            const unsigned d = key_digit<BITS>(sx[i], sz[i], n, shift);
             const long long g = (long long)goff[d] + (i - (long long)tpre[d]);
             xo[g] = sx[i];
             zo[g] = sz[i];
@@ -898,9 +907,57 @@ static int grid_for(const SparseBuffers &b) {
 }
 
 template <typename V>
-static void launch_scan(V *a, const long long *count, int mult, SparseBuffers &b, long long *total, hipStream_t s) {
-    hipLaunchKernelGGL(scan_reduce_kernel<V>, dim3(SCAN_BLOCKS), dim3(1024), 0, s, a, count, mult, b.scan);
-    hipLaunchKernelGGL(scan_apply_kernel<V>, dim3(SCAN_BLOCKS), dim3(1024), 0, s, a, count, mult, b.scan, total);
+static void launch_scan(V *a, const long long *count, int mult, SparseBuffers &b, long long *total, hipStream_t s,
+                        int tile = SP_TILE) {
+    hipLaunchKernelGGL(scan_reduce_kernel<V>, dim3(SCAN_BLOCKS), dim3(1024), 0, s, a, count, mult, tile, b.scan);
+    hipLaunchKernelGGL(scan_apply_kernel<V>, dim3(SCAN_BLOCKS), dim3(1024), 0, s, a, count, mult, tile, b.scan,
+                       total);
+}
+
+// Sort shapes (key bits per pass, terms per thread); entry 0 is the default.
+struct SortShapeDef {
+    int bits, items;
+};
+constexpr SortShapeDef kSortShapes[kSortShapeCount] = {{8, 8}, {8, 4}, {8, 16}, {7, 8}, {7, 16}, {6, 16}};
+static int g_sort_shape[kSortClasses] = {0, 0, 0};
+
+int sort_shape_class(long long cap2) { return cap2 <= (1ll << 18) ? 0 : (cap2 <= (1ll << 22) ? 1 : 2); }
+void set_sort_shape(int cls, int shape) { g_sort_shape[cls] = shape; }
+int sort_shape(int cls) { return g_sort_shape[cls]; }
+
+long long sort_hist_entries(long long cap2) {
+    long long most = 0;
+    for (const SortShapeDef &d : kSortShapes) {
+        const long long tile = (1ll << d.bits) * d.items;
+        most = std::max(most, (1ll << d.bits) * ((cap2 + tile - 1) / tile));
+    }
+    return most;
+}
+
+// One LSD pass on key bits [shift, shift + BITS): histogram, scan, stable
+// scatter into the second buffers, then the buffers swap.
+template <int BITS, int ITEMS>
+static void sort_pass(SparseBuffers &b, int n, int dtype_bytes, int shift, long long *total, hipStream_t s) {
+    constexpr int BLOCK = 1 << BITS, TILE = BLOCK * ITEMS;
+    const long long tiles = (b.cap2 + TILE - 1) / TILE;
+    const int g = (int)std::max<long long>(1, std::min<long long>(tiles, SP_GRID));
+    hipLaunchKernelGGL((sort_hist_kernel<BITS, ITEMS>), dim3(g), dim3(BLOCK), 0, s, b.x, b.z, b.count, n, shift,
+                       b.hist);
+    launch_scan<unsigned>(b.hist, b.count, BLOCK, b, total, s, TILE);
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL((sort_scatter_kernel<double, BITS, ITEMS>), dim3(g), dim3(BLOCK), 0, s, b.x, b.z, b.c,
+                           b.x2, b.z2, b.c2, b.count, n, shift, b.hist);
+    else
+        hipLaunchKernelGGL((sort_scatter_kernel<float, BITS, ITEMS>), dim3(g), dim3(BLOCK), 0, s, b.x, b.z, b.c,
+                           b.x2, b.z2, b.c2, b.count, n, shift, b.hist);
+    std::swap(b.x, b.x2);
+    std::swap(b.z, b.z2);
+    std::swap(b.c, b.c2);
+}
+
+template <int BITS, int ITEMS>
+static void sort_all(SparseBuffers &b, int n, int dtype_bytes, long long *total, hipStream_t s) {
+    for (int shift = 0; shift < 2 * n; shift += BITS) sort_pass<BITS, ITEMS>(b, n, dtype_bytes, shift, total, s);
 }
 
 hipError_t launch_sparse_init(SparseBuffers &b, int dtype_bytes, const uint64_t *x, const uint64_t *z,
@@ -939,20 +996,14 @@ hipError_t launch_sparse_pass(SparseBuffers &b, int dtype_bytes, const uint32_t 
 
 hipError_t launch_sparse_merge(SparseBuffers &b, int n, int dtype_bytes, hipStream_t s, const SparseTrunc &tr) {
     const int g = grid_for(b);
-    const int key_bits = 2 * n;
     long long *old_count = b.count + 3, *total = b.count + 4;
-    for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
-        hipLaunchKernelGGL(sort_hist_kernel, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.count, n, shift, b.hist);
-        launch_scan<unsigned>(b.hist, b.count, RADIX, b, total, s);
-        if (dtype_bytes == 8)
-            hipLaunchKernelGGL(sort_scatter_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2,
-                               b.c2, b.count, n, shift, b.hist);
-        else
-            hipLaunchKernelGGL(sort_scatter_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, b.x, b.z, b.c, b.x2, b.z2,
-                               b.c2, b.count, n, shift, b.hist);
-        std::swap(b.x, b.x2);
-        std::swap(b.z, b.z2);
-        std::swap(b.c, b.c2);
+    switch (g_sort_shape[sort_shape_class(b.cap2)]) {
+    case 1: sort_all<8, 4>(b, n, dtype_bytes, total, s); break;
+    case 2: sort_all<8, 16>(b, n, dtype_bytes, total, s); break;
+    case 3: sort_all<7, 8>(b, n, dtype_bytes, total, s); break;
+    case 4: sort_all<7, 16>(b, n, dtype_bytes, total, s); break;
+    case 5: sort_all<6, 16>(b, n, dtype_bytes, total, s); break;
+    default: sort_all<8, 8>(b, n, dtype_bytes, total, s); break;
     }
     int *bc = b.tile_flags;
     const int on = tr.on ? 1 : 0;

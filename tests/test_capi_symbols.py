@@ -126,3 +126,25 @@ def test_planner_self_check_random(n):
                 ops, passes = L.plan_dense_info(n, w.op, w.q0, w.q1, w.param, w.n_params, k, compose=compose,
                                                 reorder=compose)
                 assert ops >= 1 and passes >= 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpauliprop.so not built")
+def test_tuning_knobs_validate_without_gpu():
+    """pp_tune_set / pp_tune_get only touch host tables: every key accepts its
+    documented range and rejects the rest (PP_ERR_INVALID = 1)."""
+    from paper_2502_10685_amd import _lib as L
+    lib = L.load()
+    v = ctypes.c_int32(-1)
+    for cls in range(3):
+        old = L.tune_get(L.PP_TUNE_SORT_SHAPE, cls)
+        assert old == 0  # default shape: 8 key bits per pass, 8 terms per thread
+        for shape in range(6):
+            assert lib.pp_tune_set(L.PP_TUNE_SORT_SHAPE, cls, shape) == 0
+            assert lib.pp_tune_get(L.PP_TUNE_SORT_SHAPE, cls, ctypes.byref(v)) == 0 and v.value == shape
+        L.tune_set(L.PP_TUNE_SORT_SHAPE, cls, old)
+    for bad in ((-1, 0), (3, 0), (0, -1), (0, 6)):
+        assert lib.pp_tune_set(L.PP_TUNE_SORT_SHAPE, *bad) == 1
+    assert lib.pp_tune_get(L.PP_TUNE_SORT_SHAPE, 3, ctypes.byref(v)) == 1
+    assert lib.pp_tune_set(L.PP_TUNE_TILE_KERNEL, 7, 2) == 1  # wave-per-tile needs k <= 6
+    assert lib.pp_tune_set(L.PP_TUNE_RESIDENT_BLOCK, 6, 300) == 1
+    assert lib.pp_tune_set(99, 0, 0) == 1

@@ -21,6 +21,7 @@ def test_autotune_applies_and_caches(tmp_path, monkeypatch):
     saved = {k: L.tune_get(L.PP_TUNE_TILE_KERNEL, k) for k in (4, 5, 6)}
     saved_q = {n: L.tune_get(L.PP_TUNE_TILE_QUBITS, n) for n in (8, 9)}
     saved_b = L.tune_get(L.PP_TUNE_RESIDENT_BLOCK, 6)
+    saved_s = {c: L.tune_get(L.PP_TUNE_SORT_SHAPE, c) for c in range(3)}
     try:
         table = autotune.tune(sizes=(8, 9), m=150, resident=(6,))
         assert L.tune_get(L.PP_TUNE_RESIDENT_BLOCK, 6) == table["resident_block"]["6"]
@@ -28,8 +29,17 @@ def test_autotune_applies_and_caches(tmp_path, monkeypatch):
             assert L.tune_get(L.PP_TUNE_TILE_KERNEL, int(k)) == v
         for n, k in table["tile_qubits"].items():
             assert L.tune_get(L.PP_TUNE_TILE_QUBITS, int(n)) == k
+        assert set(table["sort_shape"]) == {"0", "1", "2"}
+        for cls, v in table["sort_shape"].items():
+            assert L.tune_get(L.PP_TUNE_SORT_SHAPE, int(cls)) == v
         with open(tmp_path / "tune.json") as f:
-            assert json.load(f)["tile_qubits"] == table["tile_qubits"]
+            cached = json.load(f)
+        assert cached["tile_qubits"] == table["tile_qubits"] and cached["sort_shape"] == table["sort_shape"]
+        for c in range(3):  # a cached table is applied on load
+            L.tune_set(L.PP_TUNE_SORT_SHAPE, c, 0)
+        autotune.load_cached()
+        for cls, v in table["sort_shape"].items():
+            assert L.tune_get(L.PP_TUNE_SORT_SHAPE, int(cls)) == v
         rng = np.random.default_rng(77)
         wc = W.random_circuit(rng, 9, 300, W.obs_z(9, [0, 2]))
         c = api.Circuit.from_workload(wc)
@@ -41,3 +51,5 @@ def test_autotune_applies_and_caches(tmp_path, monkeypatch):
         for n, k in saved_q.items():
             L.tune_set(L.PP_TUNE_TILE_QUBITS, n, k)
         L.tune_set(L.PP_TUNE_RESIDENT_BLOCK, 6, saved_b)
+        for c, v in saved_s.items():
+            L.tune_set(L.PP_TUNE_SORT_SHAPE, c, v)

@@ -126,3 +126,58 @@ def test_sparse_graph_replay_matches_eager(api):
     assert abs(e1 - oracle.expval_sv(wc.with_theta(th))) <= TOL64
     for c in (eager, graph, other):
         c.close()
+
+
+def _sort_merge_run(api, wc, shape, dtype="f64", cap=1 << 23):
+    from paper_2502_10685_amd import _lib as L
+    old = [L.tune_get(L.PP_TUNE_SORT_SHAPE, c) for c in range(3)]
+    try:
+        for c in range(3):
+            L.tune_set(L.PP_TUNE_SORT_SHAPE, c, shape)
+        circ = api.Circuit.from_workload(wc, engine="sparse", dtype=dtype, max_terms=cap)
+        circ.set_option(L.PP_OPT_SPARSE_FRAME, 0)
+        ev = float(circ.evaluate().item())
+        x, z, v = circ.terms(capacity=cap)
+        st = circ.stats()
+        circ.close()
+    finally:
+        for c in range(3):
+            L.tune_set(L.PP_TUNE_SORT_SHAPE, c, old[c])
+    return ev, x, z, v, st
+
+
+@pytest.mark.parametrize("n,m,seed", [(12, 260, 2), (3, 40, 5), (40, 90, 6)])
+def test_sort_shapes_identical(api, n, m, seed):
+    """Every radix-sort shape of the sort-merge engine (key bits per pass x
+    terms per thread) is a stable sort on the same key, so strings, weights,
+    <O> and U are identical bit for bit; shape 0 matches the oracle.  Sizes:
+    more than 50 tiles with a ragged tail, fewer strings than one tile, and
+    n = 40 (80-bit keys, past the frame engine)."""
+    wc = W.random_circuit(np.random.default_rng(seed), n, m, W.obs_z(n, [0, n - 1]))
+    ref = None
+    for shape in range(6):
+        _say(f"sort shape {shape} n={n} m={m}")
+        ev, x, z, v, st = _sort_merge_run(api, wc, shape)
+        assert not st["overflow"]
+        if ref is None:
+            ref = (ev, x, z, v, st["term_updates"])
+            want = oracle.propagate(wc, cap=1 << 23)
+            assert abs(ev - want.expval) <= TOL64
+            assert np.array_equal(x, want.x) and np.array_equal(z, want.z)
+            assert float(np.max(np.abs(v - want.c))) <= TOL64
+            assert st["term_updates"] == want.updates
+            continue
+        assert np.float64(ev).view(np.uint64) == np.float64(ref[0]).view(np.uint64)
+        assert np.array_equal(x, ref[1]) and np.array_equal(z, ref[2])
+        assert np.array_equal(v.view(np.uint64), ref[3].view(np.uint64))
+        assert st["term_updates"] == ref[4]
+
+
+def test_sort_shapes_identical_fp32(api):
+    wc = W.random_circuit(np.random.default_rng(8), 11, 230, W.obs_z(11, [0, 1]))
+    _say("sort shapes fp32 n=11")
+    a = _sort_merge_run(api, wc, 0, dtype="f32")
+    for shape in (2, 5):
+        b = _sort_merge_run(api, wc, shape, dtype="f32")
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        assert np.array_equal(a[3].view(np.uint64), b[3].view(np.uint64))
