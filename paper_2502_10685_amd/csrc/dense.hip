@@ -433,21 +433,27 @@ constexpr LaneOrder lane_order() {
     return o;
 }
 
+// A 3x3 map into SGPRs by scalar loads (the map array is read-only).
+typedef const __attribute__((address_space(4))) double *ConstMaps;
+__device__ __forceinline__ void load_map(double (&m)[9], ConstMaps src) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) m[q] = src[q];
+}
+
 // The eight common GROUP shapes (see the planner's group_shape): the CX,
-// then the U1 ops in order, with maps m1 and m2 of the first and second U1.
+// then the U1 ops in order, with maps at s1 and s2 for the first and second
+// U1.  The second map is loaded once the first is applied, so only one map
+// occupies SGPRs at a time (two would push the kernel past its SGPR budget
+// and spill).
 template <bool CTRL_LO, int CODE>
-__device__ __forceinline__ void shape_apply(double *v, const double (&m1)[9], const double (&m2)[9]) {
+__device__ __forceinline__ void shape_apply(double *v, ConstMaps s1, ConstMaps s2) {
+    double m[9];
+    load_map(m, s1);
     cx_regs<CTRL_LO>(v);
-    if constexpr (CODE == 0) {
-        u1_regs_m<true>(v, m1);
-    } else if constexpr (CODE == 1) {
-        u1_regs_m<false>(v, m1);
-    } else if constexpr (CODE == 2) {
-        u1_regs_m<true>(v, m1);
-        u1_regs_m<false>(v, m2);
-    } else {
-        u1_regs_m<false>(v, m1);
-        u1_regs_m<true>(v, m2);
+    u1_regs_m<CODE == 0 || CODE == 2>(v, m);
+    if constexpr (CODE >= 2) {
+        load_map(m, s2);
+        u1_regs_m<CODE == 3>(v, m);
     }
 }
 
@@ -492,20 +498,13 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
         double v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))];
-        if constexpr (NG >= 64) {
+        if constexpr (NG >= 64 && sizeof(T) == 8) {  // FP32 tiles keep the member loop (register budget)
             if (shape != 0) {
-                typedef const __attribute__((address_space(4))) double *CD;
-                const CD s1 = (CD)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, 1);
-                const CD s2 = (CD)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, cnt > 2 ? 2 : 1);
-                double m1[9], m2[9];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    m1[q] = s1[q];
-                    m2[q] = s2[q];
-                }
+                const ConstMaps s1 = (ConstMaps)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, 1);
+                const ConstMaps s2 = (ConstMaps)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, cnt > 2 ? 2 : 1);
 #define PP_SHAPE_CASE(S_, LO_, CODE_)                                                                          \
     case S_:                                                                                                   \
-        shape_apply<LO_, CODE_>(v, m1, m2);                                                                    \
+        shape_apply<LO_, CODE_>(v, s1, s2);                                                                    \
         _Pragma("unroll") for (int e = 0; e < 16; ++e) lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))] = \
             (T)v[e];                                                                                           \
         continue;
@@ -843,8 +842,14 @@ __device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ 
         t >>= 2;
     }
     // the thread index supplies the low bits of the slot index (digits 0-3,
-    // and the low bit of digit 4 for 512 threads); deposits of disjoint bits OR
-    return TileLoc{d, base, (unsigned)deposit_digits(tid, qubits, 0, BLOCK > 256 ? 5 : 4) * (unsigned)sizeof(T)};
+    // and the low bit of digit 4 for 512 threads); deposits of disjoint bits
+    // OR.  In 32 bits (the offset is below 2^31 bytes): 64-bit digit values
+    // would be hoisted out of the tile loop and spilled.
+    unsigned voff = 0;
+#pragma unroll
+    for (int j = 0; j < (BLOCK > 256 ? 5 : 4); ++j)
+        voff |= (((unsigned)tid >> (2 * j)) & 3u) << (2 * (unsigned)((qubits >> (8 * j)) & 0xff));
+    return TileLoc{d, base, voff * (unsigned)sizeof(T)};
 }
 
 template <typename T, int K, int BLOCK>
