@@ -495,9 +495,20 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
             wl = ow[0];
             ml = ow[2];
         }
+        // Slot sv ^ c of the block, with c = cl | ch (cl the bits below 5,
+        // ch the rest, which sv does not have): the tile starts on a 256-byte
+        // boundary of LDS (every kernel aligns its dynamic LDS so), so its
+        // byte address is ((base + sv * size) ^ cl * size) + ch * size, one
+        // XOR per slot with ch * size in the instruction's offset field.
+        typedef __attribute__((address_space(3))) T LT;
+        const unsigned svb = (unsigned)(size_t)(LT *)lc + (unsigned)sv * (unsigned)sizeof(T);
+        auto slot = [&](int e) -> LT & {
+            const int c = sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)));
+            return *(LT *)(size_t)((svb ^ (unsigned)((c & 31) * (int)sizeof(T))) + (unsigned)((c & ~31) * (int)sizeof(T)));
+        };
         double v[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = (double)lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))];
+        for (int e = 0; e < 16; ++e) v[e] = (double)slot(e);
         if constexpr (NG >= 64 && sizeof(T) == 8) {  // FP32 tiles keep the member loop (register budget)
             if (shape != 0) {
                 const ConstMaps s1 = (ConstMaps)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, 1);
@@ -505,8 +516,7 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
 #define PP_SHAPE_CASE(S_, LO_, CODE_)                                                                          \
     case S_:                                                                                                   \
         shape_apply<LO_, CODE_>(v, s1, s2);                                                                    \
-        _Pragma("unroll") for (int e = 0; e < 16; ++e) lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))] = \
-            (T)v[e];                                                                                           \
+        _Pragma("unroll") for (int e = 0; e < 16; ++e) slot(e) = (T)v[e];                                      \
         continue;
                 switch (shape) {
                     PP_SHAPE_CASE(1, true, 0)
@@ -553,7 +563,7 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
             }
         }
 #pragma unroll
-        for (int e = 0; e < 16; ++e) lc[sv ^ sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)))] = (T)v[e];
+        for (int e = 0; e < 16; ++e) slot(e) = (T)v[e];
     }
 }
 
@@ -651,7 +661,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
 // final weights / presence for pp_get_terms.
 template <typename T, bool TRACK, int N, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((N >= 7 && BLOCK <= 256) ? 2 : (BLOCK >= 1024 ? 4 : (BLOCK >= 512 ? 2 : 4))))) void resident_kernel(const ResidentDesc *__restrict__ descs) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(256) unsigned char smem[];
     __shared__ double redd[BLOCK / 64];
     __shared__ long long redi[BLOCK / 64];
     __shared__ OpCache oc;
@@ -713,7 +723,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((N >= 7 &
 // that equal their qubit form contiguous runs in HBM.
 template <typename T, bool TRACK, int K, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((BLOCK == 64 && K >= 6) ? 1 : (K >= 7 ? 2 : 4)))) void tile_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(256) unsigned char smem[];
     __shared__ long long redi[BLOCK / 64];
     __shared__ OpCache oc;
     const int b = blockIdx.x;
@@ -876,7 +886,7 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
     constexpr int size = 1 << (2 * K);
     constexpr int PER = size / BLOCK;
     static_assert(K >= 4, "the thread index supplies four digits");
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(256) unsigned char smem[];
     __shared__ long long redi[BLOCK / 64];
     __shared__ OpCacheN<kStreamOps> oc;
     T *lc = reinterpret_cast<T *>(smem);
@@ -1348,7 +1358,7 @@ __device__ double join_part(const double *lc, const double *lr, int a, int axis,
 
 template <int K, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void grad_kernel(const GradPassDesc *__restrict__ desc) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(256) unsigned char smem[];
     __shared__ double redd[BLOCK / 64];
     __shared__ OpCache oc;
     const GradPassDesc d = *desc;
@@ -1462,7 +1472,7 @@ __device__ __forceinline__ unsigned long long spread_bits(unsigned v) {
 template <typename T>
 __global__ __launch_bounds__(256) void density_decode_kernel(const T *__restrict__ coef, int n,
                                                              double *__restrict__ rho) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(256) unsigned char smem[];
     const int N = 1 << n;
     double *re = reinterpret_cast<double *>(smem);
     double *im = re + N;
