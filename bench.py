@@ -245,7 +245,7 @@ def gradient_leg(api, torch):
     return rec, {"circuit": wc, "adjoint": g_adj, "psr": g_psr, "expval": float(ev.item())}
 
 
-def sparse_leg(api, torch):
+def sparse_leg(api, torch, engines=("frame", "graph", "sortmerge")):
     """The SPARSE engine past the dense range (n = 20, 4^n slots): a seeded
     300-gate random circuit (2.66M strings at the end) and the spread circuit
     (n = 20, RY on 5 qubits: 7,962,624 strings).  Each is timed with the
@@ -261,6 +261,9 @@ def sparse_leg(api, torch):
     for name, wc in cases:
         row = {"workload": name, "gates": wc.m}
         for frame, graph in ((1, False), (1, True), (0, False)):
+            if (frame, graph) != (1, False) and {(1, True): "graph", (0, False): "sortmerge"}[(frame, graph)] \
+                    not in engines:
+                continue
             c = api.Circuit.from_workload(wc, engine="sparse", max_terms=1 << 24, use_graph=graph)
             c.set_option(L.PP_OPT_SPARSE_FRAME, frame)
             c.evaluate()
@@ -289,6 +292,8 @@ def sparse_leg(api, torch):
                     "expval_abs_diff_vs_frame": abs(float(ev.item()) - row["expval"])}
             c.close()
         out.append(row)
+    if "sortmerge" not in engines:
+        return out
     # truncated propagation past the exact method's reach (approximate; the
     # dropped weight bounds the error of <O>)
     wc = W.random_circuit(np.random.default_rng(32), 32, 400, W.obs_z(32, [0, 1]))
@@ -494,6 +499,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
     ap.add_argument("--no-sparse", action="store_true", help="skip the SPARSE engine leg")
+    ap.add_argument("--sparse-engines", default="frame,graph,sortmerge",
+                    help="parts of the SPARSE leg: the Clifford-frame engine eager (always), 'graph' (the same "
+                         "replayed as a hipGraph), 'sortmerge' (the sort-merge engine and the truncated run)")
     ap.add_argument("--no-density", action="store_true", help="skip the density-matrix (toDM) leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed batch leg")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -702,7 +710,7 @@ def main():
 
     if not args.no_sparse and args.workload == "batch512":
         log("sparse engine: n = 20")
-        res["sparse"] = sparse_leg(api, torch)
+        res["sparse"] = sparse_leg(api, torch, tuple(args.sparse_engines.split(",")))
         for r in res["sparse"]:
             log(f"sparse {r['workload']}: {r['ms']:.2f} ms"
                 + (f" ({r['ms_graph']:.2f} ms as a graph)" if "ms_graph" in r else "")
