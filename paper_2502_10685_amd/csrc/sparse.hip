@@ -671,9 +671,14 @@ __device__ __forceinline__ double frame_merge2(double p, double q) {
     return (double)(T)p + (double)(T)q;
 }
 
+// Whole 16-byte slots (key empty, position 0) in one store each: writing
+// only the key word would leave every cache line half written, which the
+// memory side completes with a read.
 __global__ void frame_clear_kernel(uint64_t *__restrict__ index, long long slots) {
+    FrameSlot *sl = reinterpret_cast<FrameSlot *>(index);
+    const FrameSlot empty = {kFrameEmpty, 0ull};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < slots; i += (long long)gridDim.x * blockDim.x)
-        index[2 * i] = kFrameEmpty;
+        sl[i] = empty;
 }
 
 // The observable into the list and the index (one thread, in term order;
