@@ -378,7 +378,11 @@ __device__ __forceinline__ void stage_ops(OpCacheN<CH> *oc, const DOp *ops, cons
 // pos[0..2(K-2)).  The first five positions are the first five free index
 // bits (in lexicographic order of their positions) whose images under sw
 // are independent modulo 32, so the 32 lanes of a half-wave hit 32
-// distinct bank pairs; the other free bits follow in ascending order.
+// distinct bank pairs; the other free bits follow in ascending order.  In a
+// 6-digit tile a pair of digits below 5 draws the lanes from the other
+// digits below 5 only, so u's bits 6 and 7 (the wave of a 256-thread sweep)
+// are digit 5: each wave then reads and writes only the quarter of the tile
+// whose digit 5 is its index.
 struct LaneOrder {
     int pos[14];
     bool conflict_free;  // the first five positions were found
@@ -414,11 +418,13 @@ constexpr LaneOrder lane_order() {
     LaneOrder o{};
     for (int j = 0; j < nf; ++j) o.pos[j] = fr[j];
     if (nf < 5) return o;
-    for (int i0 = 0; i0 < nf; ++i0)
-        for (int i1 = i0 + 1; i1 < nf; ++i1)
-            for (int i2 = i1 + 1; i2 < nf; ++i2)
-                for (int i3 = i2 + 1; i3 < nf; ++i3)
-                    for (int i4 = i3 + 1; i4 < nf; ++i4) {
+    // digit 5's two bits come last in fr when the pair avoids it
+    const int ns = (K == 6 && B < 5) ? nf - 2 : nf;
+    for (int i0 = 0; i0 < ns; ++i0)
+        for (int i1 = i0 + 1; i1 < ns; ++i1)
+            for (int i2 = i1 + 1; i2 < ns; ++i2)
+                for (int i3 = i2 + 1; i3 < ns; ++i3)
+                    for (int i4 = i3 + 1; i4 < ns; ++i4) {
                         const int idx[5] = {i0, i1, i2, i3, i4};
                         int c[5] = {0};
                         for (int k = 0; k < 5; ++k) c[k] = sw(1 << fr[idx[k]]) & 31;
@@ -472,6 +478,7 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
     constexpr LaneOrder lo = lane_order<K, A, B>();
     static_assert(K < 5 || lo.conflict_free, "every digit pair of a 5- to 7-digit tile has a conflict-free lane order");
+    static_assert(K != 6 || B == 5 || (lo.pos[6] == 10 && lo.pos[7] == 11), "waves split 6-digit tiles by digit 5");
     if (NG < BLOCK && tid >= NG) return;
 #pragma unroll 1
     for (int j = 0; j < GPT; ++j) {
@@ -597,6 +604,23 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
+// Untracked 256-thread sweeps of a 6-digit tile: an op on digits below 5
+// reads and writes only the quarter of the tile that belongs to the
+// sweeping thread's wave (digit 5 = wave index, see lane_order), so between
+// two such ops no workgroup barrier is needed.  The planner marks each op
+// after which the barrier can go (kSkipBarrier in its perm field; it moves
+// the pass's cheapest digit to position 5 first).  The LDS completes a
+// wave's instructions in issue order, and fences at wavefront scope keep
+// the compiler from moving the next op's accesses above this op's.
+template <int K, int BLOCK, bool TRACK>
+constexpr bool kWaveSplit = K == 6 && BLOCK == 256 && !TRACK;
+
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 template <typename T, bool TRACK, int K, int BLOCK, int CH = OPCH>
 __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restrict__ ops, const double *__restrict__ maps, int o0,
                         int o1, long long &tcount, long long &updates, long long *redi, OpCacheN<CH> *oc,
@@ -618,7 +642,8 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
             const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[0]);
             const uint32_t w1 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[1]);
             const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, b = (w0 >> 16) & 0xff, ngates = (w0 >> 24) & 0xff;
-            const unsigned smask = w1 & 0xffff, perm = w1 >> 16;
+            const unsigned smask = w1 & 0xffff, perm = (w1 >> 16) & ~kSkipBarrier;
+            const bool skip_barrier = kWaveSplit<K, BLOCK, TRACK> && ((w1 >> 16) & kSkipBarrier);
             if (kind == DOP_SEG) {  // register-tile layout hint: nothing to do in LDS
                 ++i;
                 continue;
@@ -649,7 +674,8 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
                 if (TRACK) updates += tcount * ngates;
                 ++i;
             }
-            lds_barrier();
+            if (skip_barrier) wave_lds_order();
+            else lds_barrier();
         }
         cb += i;
     }

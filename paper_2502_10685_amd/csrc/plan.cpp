@@ -193,14 +193,107 @@ std::vector<DOp> segment_ops(const std::vector<DOp> &in, int k) {
     return out;
 }
 
+// Digits an op's LDS sweep covers that matter for the wave split: a lone U1
+// on digit a is swept with digit a - 1 (digit 1 for a = 0), which is digit 5
+// only when a is.
+unsigned sweep_digits(const DOp &d) {
+    return d.kind == DOP_U1 ? 1u << d.a : (1u << d.a) | (1u << d.b);
+}
+
+// Workgroup barriers between consecutive LDS ops of a pass if the waves of a
+// 256-thread sweep split the tile by digit D: one is skipped only between
+// two ops that both avoid D.
+int split_barriers(const std::vector<DOp> &ops, int D) {
+    int count = 0;
+    bool have_prev = false, prev_avoids = false;
+    for (size_t i = 0; i < ops.size();) {
+        const DOp &d = ops[i];
+        if (d.kind == DOP_SEG) {
+            ++i;
+            continue;
+        }
+        const bool avoids = !((sweep_digits(d) >> D) & 1u);
+        if (have_prev && !(prev_avoids && avoids)) ++count;
+        have_prev = true;
+        prev_avoids = avoids;
+        i += d.kind == DOP_GROUP ? 1 + d.ngates : 1;
+    }
+    return count;
+}
+
+// 6-digit tiles: the kernels that sweep them with 256 threads give each wave
+// the quarter of the tile whose digit 5 is the wave's index and skip the
+// workgroup barrier between two consecutive ops that avoid digit 5.  This
+// renames the tile digits of the pass so that the digit among 2..5 that
+// costs the fewest barriers becomes digit 5 (the digits above it move down
+// by one; digits 0 and 1, the two lowest qubits that give the tile its
+// 128-byte runs in HBM, keep their places), then marks every op after which
+// the barrier can go.
+void split_waves(std::vector<DOp> &ops, DensePass &ps) {
+    int best = 5, best_count = split_barriers(ops, 5);
+    for (int D = 2; D < 5; ++D) {
+        const int c = split_barriers(ops, D);
+        if (c < best_count) {
+            best = D;
+            best_count = c;
+        }
+    }
+    if (best != 5) {
+        uint8_t to[8];
+        for (int d = 0; d < 8; ++d) to[d] = (uint8_t)(d < best ? d : (d == best ? 5 : (d <= 5 ? d - 1 : d)));
+        for (size_t i = 0; i < ops.size();) {
+            DOp &h = ops[i];
+            if (h.kind == DOP_SEG) {
+                uint8_t t[3] = {to[h.a], to[h.b], to[h.smask]};
+                std::sort(t, t + 3);
+                h.a = t[0];
+                h.b = t[1];
+                h.smask = t[2];
+                ++i;
+            } else if (h.kind == DOP_GROUP) {
+                const uint8_t a = to[h.a], b = to[h.b];
+                h.a = std::min(a, b);
+                h.b = std::max(a, b);
+                for (int j = 1; j <= h.ngates; ++j) {
+                    DOp &m = ops[i + j];
+                    m.a = to[m.a];
+                    if (m.kind == DOP_CX) m.b = to[m.b];
+                }
+                h.perm = (uint16_t)group_shape(&ops[i + 1], h.ngates, h.a);
+                i += 1 + h.ngates;
+            } else {
+                h.a = to[h.a];
+                if (h.kind == DOP_CX) h.b = to[h.b];
+                ++i;
+            }
+        }
+        uint8_t q[8];
+        for (int d = 0; d < ps.k; ++d) q[to[d]] = ps.qubit[d];
+        for (int d = 0; d < ps.k; ++d) ps.qubit[d] = q[d];
+    }
+    DOp *prev = nullptr;
+    for (size_t i = 0; i < ops.size();) {
+        DOp &d = ops[i];
+        if (d.kind == DOP_SEG) {
+            ++i;
+            continue;
+        }
+        const bool avoids = !((sweep_digits(d) >> 5) & 1u);
+        if (prev && avoids && !((sweep_digits(*prev) >> 5) & 1u)) prev->perm |= (uint16_t)kSkipBarrier;
+        prev = &d;
+        i += d.kind == DOP_GROUP ? 1 + d.ngates : 1;
+    }
+}
+
 void group_all(DensePlan &P) {
     int shift = 0;
     for (DensePass &ps : P.passes) {
         ps.op_begin += shift;
         ps.op_end += shift;
         const std::vector<DOp> in(P.ops.begin() + ps.op_begin, P.ops.begin() + ps.op_end);
-        const std::vector<DOp> out =
+        std::vector<DOp> out =
             (!P.resident && ps.k == kSegTileDigits) ? segment_ops(in, ps.k) : group_ops(in, ps.k);
+        if (!P.resident && ps.k == 6) split_waves(out, ps);
         P.ops.erase(P.ops.begin() + ps.op_begin, P.ops.begin() + ps.op_end);
         P.ops.insert(P.ops.begin() + ps.op_begin, out.begin(), out.end());
         const int added = (int)out.size() - (int)in.size();
@@ -475,8 +568,17 @@ std::string plan_check(const DensePlan &P, int n) {
         expect = ps.op_end;
         const int k = ps.k;
         if (k < 1 || k > n || (k < n && k > 8)) return "bad tile size";
-        for (int j = 1; j < k && j < 8; ++j)
-            if (ps.qubit[j] <= ps.qubit[j - 1] || ps.qubit[j] >= n) return "tile qubits not ascending";
+        // ascending, except that a 6-digit tile may carry any of its qubits
+        // but the two lowest as digit 5
+        uint64_t seen = 0;
+        for (int j = 0; j < k && j < 8; ++j) {
+            if (ps.qubit[j] >= n || ((seen >> ps.qubit[j]) & 1u)) return "tile qubits not distinct";
+            seen |= 1ull << ps.qubit[j];
+        }
+        const int ordered = (!P.resident && k == 6) ? 5 : k;
+        for (int j = 1; j < ordered && j < 8; ++j)
+            if (ps.qubit[j] <= ps.qubit[j - 1]) return "tile qubits not ascending";
+        if (ordered < k && ps.qubit[5] < ps.qubit[1]) return "a lowest qubit moved to digit 5";
         const bool segmented = ps.op_begin < ps.op_end && P.ops[ps.op_begin].kind == DOP_SEG;
         if (segmented && (P.resident || k != kSegTileDigits)) return "SEG header outside a register-tile pass";
         int seg_end = ps.op_begin;
@@ -508,7 +610,8 @@ std::string plan_check(const DensePlan &P, int n) {
                     if (m.kind == DOP_CX && ((m.b != d.a && m.b != d.b) || m.a == m.b)) return "GROUP CX outside its pair";
                     if (m.kind == DOP_U1 && m.map >= (uint32_t)P.nmaps()) return "map index out of range";
                 }
-                if (d.perm != (uint16_t)group_shape(&P.ops[(size_t)i + 1], d.ngates, d.a)) return "GROUP shape tag";
+                if ((d.perm & ~kSkipBarrier) != (unsigned)group_shape(&P.ops[(size_t)i + 1], d.ngates, d.a))
+                    return "GROUP shape tag";
                 i += d.ngates;
                 continue;
             }

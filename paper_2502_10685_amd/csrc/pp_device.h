@@ -34,6 +34,10 @@ struct DOp {
     uint32_t reserved;
 };
 static_assert(sizeof(DOp) == 16, "DOp must stay 16 bytes");
+// Bit of DOp::perm (any op but SEG): the next op of the pass stays inside
+// one wave's quarter of a 6-digit tile as this one does, so 256-thread
+// sweeps skip the workgroup barrier between them.
+constexpr unsigned kSkipBarrier = 0x8000u;
 
 // A whole circuit run inside one workgroup's LDS (n <= 7).
 struct ResidentDesc {
