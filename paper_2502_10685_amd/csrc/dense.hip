@@ -636,14 +636,22 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
         if (!preloaded) stage_ops<CH>(oc, ops, maps, cb, cn, tid, BLOCK);
         lds_barrier();
         preloaded = false;
+        // words 0 and 1 of the next op's header are read from LDS while the
+        // current op runs, so decoding an op waits for no LDS round trip
+        typedef unsigned HdrW __attribute__((ext_vector_type(2)));
+        HdrW hdr = reinterpret_cast<const HdrW *>(&oc->ops[0])[0];
         int i = 0;
         while (i < cn) {
             // op fields are the same for every lane: keep them in SGPRs
-            const uint32_t w0 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[0]);
-            const uint32_t w1 = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t *>(&oc->ops[i])[1]);
+            const uint32_t w0 = __builtin_amdgcn_readfirstlane(hdr.x);
+            const uint32_t w1 = __builtin_amdgcn_readfirstlane(hdr.y);
             const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, b = (w0 >> 16) & 0xff, ngates = (w0 >> 24) & 0xff;
             const unsigned smask = w1 & 0xffff, perm = (w1 >> 16) & ~kSkipBarrier;
             const bool skip_barrier = kWaveSplit<K, BLOCK, TRACK> && ((w1 >> 16) & kSkipBarrier);
+            {
+                const int nxt = i + 1 + (kind == DOP_GROUP ? ngates : 0);
+                if (nxt < cn) hdr = reinterpret_cast<const HdrW *>(&oc->ops[nxt])[0];
+            }
             if (kind == DOP_SEG) {  // register-tile layout hint: nothing to do in LDS
                 ++i;
                 continue;
