@@ -447,17 +447,16 @@ __device__ __forceinline__ void load_map(double (&m)[9], ConstMaps src) {
 }
 
 // The eight common GROUP shapes (see the planner's group_shape): the CX,
-// then the U1 ops in order, with maps at s1 and s2 for the first and second
-// U1.  The second map is loaded once the first is applied, so only one map
-// occupies SGPRs at a time (two would push the kernel past its SGPR budget
-// and spill).
+// then the U1 ops in order, with the first U1's map m1 already loaded and
+// the second's at s2.  The second map is loaded once the first is applied,
+// so only one map occupies SGPRs at a time (two would push the kernel past
+// its SGPR budget and spill).
 template <bool CTRL_LO, int CODE>
-__device__ __forceinline__ void shape_apply(double *v, ConstMaps s1, ConstMaps s2) {
-    double m[9];
-    load_map(m, s1);
+__device__ __forceinline__ void shape_apply(double *v, const double (&m1)[9], ConstMaps s2) {
     cx_regs<CTRL_LO>(v);
-    u1_regs_m<CODE == 0 || CODE == 2>(v, m);
+    u1_regs_m<CODE == 0 || CODE == 2>(v, m1);
     if constexpr (CODE >= 2) {
+        double m[9];
         load_map(m, s2);
         u1_regs_m<CODE == 3>(v, m);
     }
@@ -473,7 +472,7 @@ __device__ __forceinline__ void shape_apply(double *v, ConstMaps s1, ConstMaps s
 // as the general member loop, so the same results.
 template <typename T, int K, int BLOCK, int A, int B>
 __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, int cnt, int tid, const DOp *gops,
-                                            const double *gmaps, int shape) {
+                                            const double *gmaps, int shape, uint32_t map1, uint32_t map2) {
     constexpr int NG = 1 << (2 * (K - 2));
     constexpr int GPT = NG >= BLOCK ? NG / BLOCK : 1;
     constexpr LaneOrder lo = lane_order<K, A, B>();
@@ -513,16 +512,20 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
             const int c = sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)));
             return *(LT *)(size_t)((svb ^ (unsigned)((c & 31) * (int)sizeof(T))) + (unsigned)((c & ~31) * (int)sizeof(T)));
         };
+        constexpr bool kShapes = NG >= 64 && sizeof(T) == 8;  // FP32 tiles keep the member loop (register budget)
         double v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = (double)slot(e);
-        if constexpr (NG >= 64 && sizeof(T) == 8) {  // FP32 tiles keep the member loop (register budget)
+        if constexpr (kShapes) {
             if (shape != 0) {
-                const ConstMaps s1 = (ConstMaps)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, 1);
-                const ConstMaps s2 = (ConstMaps)gmaps + 9ull * (uint32_t)__builtin_amdgcn_readlane(ml, cnt > 2 ? 2 : 1);
+                // the maps' indices came with the header: no LDS read before
+                // their scalar loads
+                double m1[9];
+                load_map(m1, (ConstMaps)gmaps + 9ull * map1);
+                const ConstMaps s2 = (ConstMaps)gmaps + 9ull * map2;
 #define PP_SHAPE_CASE(S_, LO_, CODE_)                                                                          \
     case S_:                                                                                                   \
-        shape_apply<LO_, CODE_>(v, s1, s2);                                                                    \
+        shape_apply<LO_, CODE_>(v, m1, s2);                                                                    \
         _Pragma("unroll") for (int e = 0; e < 16; ++e) slot(e) = (T)v[e];                                      \
         continue;
                 switch (shape) {
@@ -576,10 +579,12 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
 
 template <typename T, int K, int BLOCK>
 __device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops, int first, int cnt, int tid,
-                                            const DOp *gops, const double *gmaps, int shape) {
+                                            const DOp *gops, const double *gmaps, int shape, uint32_t map1 = 0,
+                                            uint32_t map2 = 0) {
 #define PP_GROUP_CASE(A_, B_)                                                                                       \
     case (A_) * 8 + (B_):                                                                                          \
-        if constexpr ((B_) < K) group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, first, cnt, tid, gops, gmaps, shape); \
+        if constexpr ((B_) < K)                                                                                    \
+            group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, first, cnt, tid, gops, gmaps, shape, map1, map2);        \
         return;
     switch (a * 8 + b) {
         PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
@@ -636,15 +641,17 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
         if (!preloaded) stage_ops<CH>(oc, ops, maps, cb, cn, tid, BLOCK);
         lds_barrier();
         preloaded = false;
-        // words 0 and 1 of the next op's header are read from LDS while the
+        // the next op's header (16 bytes) is read from LDS while the
         // current op runs, so decoding an op waits for no LDS round trip
-        typedef unsigned HdrW __attribute__((ext_vector_type(2)));
+        typedef unsigned HdrW __attribute__((ext_vector_type(4)));
         HdrW hdr = reinterpret_cast<const HdrW *>(&oc->ops[0])[0];
         int i = 0;
         while (i < cn) {
             // op fields are the same for every lane: keep them in SGPRs
             const uint32_t w0 = __builtin_amdgcn_readfirstlane(hdr.x);
             const uint32_t w1 = __builtin_amdgcn_readfirstlane(hdr.y);
+            const uint32_t w2 = __builtin_amdgcn_readfirstlane(hdr.z);
+            const uint32_t w3 = __builtin_amdgcn_readfirstlane(hdr.w);
             const int kind = w0 & 0xff, a = (w0 >> 8) & 0xff, b = (w0 >> 16) & 0xff, ngates = (w0 >> 24) & 0xff;
             const unsigned smask = w1 & 0xffff, perm = (w1 >> 16) & ~kSkipBarrier;
             const bool skip_barrier = kWaveSplit<K, BLOCK, TRACK> && ((w1 >> 16) & kSkipBarrier);
@@ -659,7 +666,7 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
             if (kind == DOP_GROUP) {
                 if (i + 1 + ngates > cn) break;  // reload the chunk from this header
                 if constexpr (K >= 2)
-                    group_apply<T, K, BLOCK>(lc, a, b, oc->ops, i + 1, ngates, tid, gops, gmaps, (int)perm);
+                    group_apply<T, K, BLOCK>(lc, a, b, oc->ops, i + 1, ngates, tid, gops, gmaps, (int)perm, w2, w3);
                 i += 1 + ngates;
             } else if (!TRACK && K >= 2 && K <= 7) {
                 // untracked U1 or CX alone: a group sweep of one op over its
@@ -976,8 +983,13 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
                                                 true);
         if (!fits) cached = nullptr;  // run_ops reloaded later chunks into oc
         T out[PER];
+        // an opaque copy of the slot base: the 16 tile addresses are
+        // recomputed per tile (16 XORs) instead of living in 16 VGPRs
+        // across the whole loop
+        int st = stid;
+        __asm__ volatile("" : "+v"(st));
 #pragma unroll
-        for (int r = 0; r < PER; ++r) out[r] = lc[stid ^ sw(r * BLOCK)];
+        for (int r = 0; r < PER; ++r) out[r] = lc[st ^ sw(r * BLOCK)];
         {
             const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(cur.d->coef) + cur.base);
             const uint64_t qubits = cur.d->qubits;
@@ -992,8 +1004,10 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
             for (int r = PE; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
         }
         lds_barrier();  // every thread has read this tile and is done with oc
+        st = stid;
+        __asm__ volatile("" : "+v"(st));
 #pragma unroll
-        for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
+        for (int r = 0; r < PER; ++r) lc[st ^ sw(r * BLOCK)] = pre[r];
         blk = nblk;
         cur = nxt;
     }

@@ -78,6 +78,16 @@ int group_shape(const DOp *m, int count, int lo) {
 
 namespace {
 
+// A GROUP of one of the eight shapes carries the map indices of its U1
+// members in its header (map: the first, reserved: the second, or the
+// first again), so a sweep can load its maps as soon as it decodes the
+// header.
+void set_shape_maps(DOp &h, const DOp *members) {
+    if (!h.perm) return;
+    h.map = members[1].map;
+    h.reserved = h.ngates > 2 ? members[2].map : members[1].map;
+}
+
 // Regroups a run of ops: repeatedly takes the first remaining op and every
 // later op whose digits stay within one pair of digits and that does not
 // share a digit with an op it would move past (ops on disjoint digits
@@ -124,6 +134,7 @@ std::vector<DOp> group_ops(const std::vector<DOp> &in, int k) {
         std::vector<DOp> body;
         for (size_t j : mem) body.push_back(in[j]);
         h.perm = (uint16_t)group_shape(body.data(), (int)body.size(), h.a);
+        set_shape_maps(h, body.data());
         out.push_back(h);
         out.insert(out.end(), body.begin(), body.end());
     }
@@ -260,6 +271,7 @@ void split_waves(std::vector<DOp> &ops, DensePass &ps) {
                     if (m.kind == DOP_CX) m.b = to[m.b];
                 }
                 h.perm = (uint16_t)group_shape(&ops[i + 1], h.ngates, h.a);
+                set_shape_maps(h, &ops[i + 1]);
                 i += 1 + h.ngates;
             } else {
                 h.a = to[h.a];
@@ -610,8 +622,11 @@ std::string plan_check(const DensePlan &P, int n) {
                     if (m.kind == DOP_CX && ((m.b != d.a && m.b != d.b) || m.a == m.b)) return "GROUP CX outside its pair";
                     if (m.kind == DOP_U1 && m.map >= (uint32_t)P.nmaps()) return "map index out of range";
                 }
-                if ((d.perm & ~kSkipBarrier) != (unsigned)group_shape(&P.ops[(size_t)i + 1], d.ngates, d.a))
-                    return "GROUP shape tag";
+                const unsigned shape = (unsigned)group_shape(&P.ops[(size_t)i + 1], d.ngates, d.a);
+                if ((d.perm & ~kSkipBarrier) != shape) return "GROUP shape tag";
+                if (shape && (d.map != P.ops[(size_t)i + 2].map ||
+                              d.reserved != P.ops[(size_t)i + (d.ngates > 2 ? 3 : 2)].map))
+                    return "GROUP shape maps";
                 i += d.ngates;
                 continue;
             }
@@ -646,6 +661,10 @@ void plan_append(DensePlan &all, const DensePlan &part) {
     const int32_t rec_off = (int32_t)all.rop.size();
     for (DOp d : part.ops) {
         if (d.kind == DOP_U1) d.map += map_off;
+        if (d.kind == DOP_GROUP && (d.perm & ~kSkipBarrier)) {  // a shape's map indices
+            d.map += map_off;
+            d.reserved += map_off;
+        }
         all.ops.push_back(d);
     }
     for (size_t i = 1; i < part.roff.size(); ++i) all.roff.push_back(part.roff[i] + rec_off);
