@@ -638,8 +638,10 @@ __device__ __forceinline__ void run_ops(T *lc, uint8_t *lp, const DOp *__restric
         const int cn = (o1 - cb) < CH ? (o1 - cb) : CH;
         const DOp *gops = gops0 + cb;  // gops[i] is oc->ops[i]
         lds_barrier();
-        if (!preloaded) stage_ops<CH>(oc, ops, maps, cb, cn, tid, BLOCK);
-        lds_barrier();
+        if (!preloaded) {
+            stage_ops<CH>(oc, ops, maps, cb, cn, tid, BLOCK);
+            lds_barrier();
+        }
         preloaded = false;
         // the next op's header (16 bytes) is read from LDS while the
         // current op runs, so decoding an op waits for no LDS round trip
