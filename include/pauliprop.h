@@ -102,7 +102,7 @@ typedef enum pp_option {
                                circuits and output array); theta is read
                                from device memory at replay */
     PP_OPT_BLOCK = 4,       /* threads per workgroup (64..1024), 0 = default */
-    PP_OPT_SPARSE_FRAME = 5 /* SPARSE, exact runs with n <= 31: 1 (default)
+    PP_OPT_SPARSE_FRAME = 5, /* SPARSE, exact runs with n <= 31: 1 (default)
                                propagates in the Clifford frame (Clifford
                                gates folded into the rotation axes on the
                                host, one kernel per rotation, duplicates
@@ -110,6 +110,22 @@ typedef enum pp_option {
                                sort-merge pass of every rotation.  Same
                                strings and weights; truncated runs and
                                n > 31 always use sort-merge */
+    PP_OPT_FRAME_RAMP = 6   /* DENSE without term tracking: t in 1..24 starts
+                               the Heisenberg sweep in the Clifford frame,
+                               where the set holds only its strings (it grows
+                               from the observable's toward 4^n, Sec. II-B),
+                               and hands the strings to the 4^n array once
+                               the set could exceed 4^n / 2^t: the frame
+                               takes the longest suffix of gates over which
+                               (observable terms) x 2^(rotations) stays
+                               within that limit, which is also the frame's
+                               capacity.  0 (default) is the 4^n array from
+                               the first gate.  Results agree within
+                               rounding (the merge order differs).  Such a
+                               circuit is evaluated one by one inside
+                               pp_evaluate_batch and served through the
+                               general path; pp_evaluate_thetas and
+                               pp_evaluate_noalloc refuse it (PP_ERR_STATE) */
 } pp_option;
 
 typedef struct pp_circuit pp_circuit;

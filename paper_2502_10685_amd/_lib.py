@@ -12,7 +12,7 @@ STATUS_NAMES = ["PP_OK", "PP_ERR_INVALID", "PP_ERR_NOMEM", "PP_ERR_DEVICE", "PP_
                 "PP_ERR_STATE", "PP_ERR_BUSY"]
 PP_F64, PP_F32 = 0, 1
 PP_ENGINE_AUTO, PP_ENGINE_DENSE, PP_ENGINE_SPARSE = 0, 1, 2
-PP_OPT_TRACK_TERMS, PP_OPT_TILE_QUBITS, PP_OPT_MAX_TERMS, PP_OPT_USE_GRAPH, PP_OPT_BLOCK, PP_OPT_SPARSE_FRAME = range(6)
+PP_OPT_TRACK_TERMS, PP_OPT_TILE_QUBITS, PP_OPT_MAX_TERMS, PP_OPT_USE_GRAPH, PP_OPT_BLOCK, PP_OPT_SPARSE_FRAME, PP_OPT_FRAME_RAMP = range(7)
 PP_TUNE_TILE_QUBITS, PP_TUNE_TILE_KERNEL, PP_TUNE_RESIDENT_BLOCK, PP_TUNE_SORT_SHAPE = 0, 1, 2, 3
 
 

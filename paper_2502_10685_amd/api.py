@@ -104,7 +104,7 @@ class Circuit:
 
     def __init__(self, n, op, q0, q1, param, n_params, obs_x, obs_z, obs_c, *, theta=None,
                  dtype="f64", engine="auto", track=False, tile_qubits=0, use_graph=False,
-                 max_terms=0):
+                 max_terms=0, frame_ramp=0):
         _require_gpu()
         self._lib = L.load()
         self.n = int(n)
@@ -124,6 +124,8 @@ class Circuit:
             self.set_option(L.PP_OPT_USE_GRAPH, 1)
         if max_terms:
             self.set_option(L.PP_OPT_MAX_TERMS, max_terms)
+        if frame_ramp:
+            self.set_option(L.PP_OPT_FRAME_RAMP, frame_ramp)
         if theta is not None:
             self.set_theta(theta)
 

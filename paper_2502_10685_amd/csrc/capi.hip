@@ -456,6 +456,9 @@ struct pp_circuit {
     // Clifford-frame engine (exact SPARSE runs with n <= 31): string list,
     // hash index, counters; its plan and the x rows of the final frame
     int frame_opt = 1;           // PP_OPT_SPARSE_FRAME
+    int ramp_opt = 0;            // PP_OPT_FRAME_RAMP (DENSE)
+    int plan_ramp_opt = 0;       // the ramp setting the plan was built with
+    int64_t ramp_gate = -1;      // DENSE ramp: gates [ramp_gate, m) run in the Clifford frame
     pp::FrameBuffers fb{};
     pp::FramePlan fplan;
     uint64_t *d_xrows = nullptr;
@@ -623,6 +626,36 @@ int tile_qubits_for(const pp_circuit *c) {
 
 // weights = false: DENSE circuits get no 4^n weight array of their own (the
 // serving loop runs them in buffers of its pool)
+// The ramp of a DENSE evaluation (PP_OPT_FRAME_RAMP = t): the Heisenberg
+// sweep starts in the Clifford frame, where the set holds only the strings
+// it has, and hands over to the 4^n array once the set could exceed 4^n /
+// 2^t strings.  A set of T strings entering a rotation leaves it with at
+// most 2T (Table I: one child per anticommuting string) and Clifford gates
+// keep its size, so `nterms * 2^(rotations so far)` bounds it; the frame
+// runs the longest Heisenberg suffix of gates whose bound stays within the
+// limit, which is also its capacity.
+bool ramp_wanted(const pp_circuit *c) {
+    return c->engine == PP_ENGINE_DENSE && c->ramp_opt > 0 && !c->track && c->n <= pp::kFrameMaxN;
+}
+int64_t ramp_limit(const pp_circuit *c) {
+    return std::max<int64_t>((int64_t)1 << std::max(0, 2 * c->n - c->ramp_opt), 1);
+}
+// First gate of the frame suffix, or m when the ramp holds no gate.
+int64_t ramp_switch_gate(const pp_circuit *c) {
+    const int64_t limit = ramp_limit(c);
+    int64_t bound = (int64_t)c->ox.size();
+    if (bound > limit) return c->g.m;
+    int64_t s = c->g.m;
+    while (s > 0) {
+        if (c->g.op[(size_t)s - 1] >= 3) {  // a rotation doubles the bound
+            if (bound > limit / 2) break;
+            bound *= 2;
+        }
+        --s;
+    }
+    return s;
+}
+
 pp_status ensure_state(pp_circuit *c, bool weights = true) {
     if (c->engine == PP_ENGINE_DENSE) {
         const int64_t slots = dense_slots(c->n);
@@ -664,9 +697,10 @@ pp_status ensure_state(pp_circuit *c, bool weights = true) {
         HIPCHK(dalloc(&c->d_dropped, (size_t)tiles + 1));
         HIPCHK(dalloc(&c->d_partials, 256));
     }
-    if (c->engine == PP_ENGINE_SPARSE && c->n <= pp::kFrameMaxN && c->frame_opt && !c->fb.keys) {
+    const bool ramp = ramp_wanted(c);
+    if (((c->engine == PP_ENGINE_SPARSE && c->n <= pp::kFrameMaxN && c->frame_opt) || ramp) && !c->fb.keys) {
         // index slots: a power of two of at least twice the list capacity
-        const int64_t cap = c->sb.cap2 / 2;
+        const int64_t cap = ramp ? ramp_limit(c) : c->sb.cap2 / 2;
         int bits = 1;
         while (((int64_t)1 << bits) < 2 * cap) ++bits;
         pp::FrameBuffers f{};
@@ -716,7 +750,7 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
     const bool frame = wants_frame(c);
     // the descriptors hold the weight pointer they were built with
     if (c->plan_valid && c->plan_track == c->track && c->plan_k == k && c->plan_coef == c->coef &&
-        c->plan_frame == frame)
+        c->plan_frame == frame && c->plan_ramp_opt == c->ramp_opt)
         return PP_OK;
     free_plan_buffers(c);
     if (c->track && c->engine == PP_ENGINE_DENSE && !c->pres) HIPCHK(dalloc(&c->pres, (size_t)dense_slots(c->n)));
@@ -728,7 +762,32 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
             if ((r = upload_vec(&c->d_xrows, c->fplan.xrows)) != PP_OK) return r;
         }
     } else {
-        c->dplan = pp::plan_dense(c->g, k, kLowQubits, c->track == 0, c->track == 0);
+        c->ramp_gate = -1;
+        if (ramp_wanted(c)) {
+            const int64_t sw = ramp_switch_gate(c);
+            if (sw < c->g.m) {
+                // the frame runs gates [sw, m) (Heisenberg order: g_m first)
+                pp::GateList suf;
+                suf.n = c->g.n;
+                suf.m = c->g.m - sw;
+                suf.n_params = c->g.n_params;
+                suf.op.assign(c->g.op.begin() + sw, c->g.op.end());
+                suf.q0.assign(c->g.q0.begin() + sw, c->g.q0.end());
+                suf.q1.assign(c->g.q1.begin() + sw, c->g.q1.end());
+                suf.param.assign(c->g.param.begin() + sw, c->g.param.end());
+                c->splan = pp::plan_sparse(suf);
+                c->fplan = pp::plan_frame(suf, c->splan);
+                if ((r = upload_vec(&c->d_codes, c->splan.codes)) != PP_OK) return r;
+                c->ramp_gate = sw;
+            }
+        }
+        if (c->ramp_gate >= 0) {
+            pp::PlanOptions o;
+            o.g_end = c->ramp_gate;  // the dense sweep takes the gates before the frame's
+            c->dplan = pp::plan_dense_opts(c->g, k, kLowQubits, o);
+        } else {
+            c->dplan = pp::plan_dense(c->g, k, kLowQubits, c->track == 0, c->track == 0);
+        }
         const pp::DensePlan &P = c->dplan;
         {
             // the kernels trust the schedule's digits and segment bounds
@@ -748,6 +807,7 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
             pp::ResidentDesc &d = c->h_res;
             d = pp::ResidentDesc{};
             d.coef_out = (c->track || c->keep_coef) ? c->coef : nullptr;
+            d.coef_in = c->ramp_gate >= 0 ? c->coef : nullptr;  // the ramp's strings
             d.pres_out = c->track ? c->pres : nullptr;
             d.ops = c->d_ops;
             d.maps = c->d_maps;
@@ -790,6 +850,7 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
     c->plan_k = k;
     c->plan_coef = c->coef;
     c->plan_frame = frame;
+    c->plan_ramp_opt = c->ramp_opt;
     c->plan_gen = ++g_plan_gen;
     return PP_OK;
 }
@@ -810,7 +871,7 @@ void fill_plan_stats(pp_circuit *c) {
         const pp::DensePlan &P = c->dplan;
         s.ops = 0;
         for (const pp::DOp &d : P.ops) s.ops += d.kind != pp::DOP_GROUP && d.kind != pp::DOP_SEG;
-        s.passes = (int64_t)P.passes.size();
+        s.passes = (int64_t)P.passes.size() + (c->ramp_gate >= 0 ? (int64_t)c->fplan.passes.size() : 0);
         s.tile_qubits = P.k;
         const int64_t slots = dense_slots(c->n);
         const int64_t per = 2 * slots * (c->dbytes + (c->track ? 1 : 0));
@@ -840,6 +901,20 @@ void fill_plan_stats(pp_circuit *c) {
 pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
     const pp::DensePlan &P = c->dplan;
     if (c->track) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, c->d_counters, 4);
+    if (c->ramp_gate >= 0) {
+        // the ramp: the gates after ramp_gate in the Clifford frame, then its
+        // strings in their actual form into the zeroed 4^n array
+        if ((int64_t)c->ox.size() > c->fb.cap) return fail(PP_ERR_CAPACITY, "observable larger than the ramp");
+        HIPCHK(pp::launch_frame_init(c->fb, c->dbytes, c->d_ox, c->d_oz, c->d_oc, (int)c->ox.size(), s));
+        const int np = (int)c->fplan.passes.size();
+        for (int i = 0; i < np; ++i) {
+            ProfScope ps(PC_SPASS, s);
+            HIPCHK(pp::launch_frame_pass(c->fb, c->dbytes, c->fplan.passes[(size_t)i], c->d_theta, i, s));
+        }
+        ProfScope ps(PC_INIT, s);
+        HIPCHK(pp::launch_dense_init(c->coef, nullptr, c->n, c->dbytes, c->d_ox, c->d_oz, c->d_oc, 0, s));
+        HIPCHK(pp::launch_frame_to_dense(c->fb, c->dbytes, c->d_codes, (int)c->splan.codes.size(), np, c->coef, s));
+    }
     if (P.nmaps() > 0) {
         ProfScope ps(PC_COMPOSE, s);
         HIPCHK(pp::launch_compose(c->d_comp, 1, s, P.nmaps()));
@@ -853,7 +928,7 @@ pp_status enqueue_dense_body(pp_circuit *c, hipStream_t s, double *out) {
         HIPCHK(hipGetLastError());
         return PP_OK;
     }
-    {
+    if (c->ramp_gate < 0) {
         ProfScope ps(PC_INIT, s);
         HIPCHK(pp::launch_dense_init(c->coef, c->track ? c->pres : nullptr, c->n, c->dbytes, c->d_ox, c->d_oz,
                                      c->d_oc, (int)c->ox.size(), s));
@@ -1232,6 +1307,20 @@ pp_status pp_circuit_set_option(pp_circuit *c, pp_option key, int64_t value) {
         c->frame_opt = value ? 1 : 0;
         free_graph(c);
         return PP_OK;
+    case PP_OPT_FRAME_RAMP:
+        if (value < 0 || value > 24) return fail(PP_ERR_INVALID, "frame ramp must be 0..24");
+        if (c->engine == PP_ENGINE_DENSE && (int)value != c->ramp_opt) {
+            free_plan_buffers(c);
+            dfree(c->fb.keys);  // the ramp's capacity follows the setting
+            dev_free(c->fb.coef);
+            dfree(c->fb.index);
+            dfree(c->fb.cnt);
+            dfree(c->fb.updates);
+            c->fb = pp::FrameBuffers{};
+        }
+        c->ramp_opt = (int)value;
+        free_graph(c);
+        return PP_OK;
     }
     return fail(PP_ERR_INVALID, "unknown option");
 }
@@ -1294,8 +1383,8 @@ pp_status pp_evaluate_noalloc(pp_circuit *c, void *stream, double *d_expval) {
     pp_status r = check_ready(c);
     if (r != PP_OK) return r;
     if (!d_expval) return fail(PP_ERR_INVALID, "d_expval is NULL");
-    if (c->engine != PP_ENGINE_DENSE || c->track)
-        return fail(PP_ERR_STATE, "pp_evaluate_noalloc runs DENSE circuits without term tracking");
+    if (c->engine != PP_ENGINE_DENSE || c->track || c->ramp_opt)
+        return fail(PP_ERR_STATE, "pp_evaluate_noalloc runs DENSE circuits without term tracking or frame ramp");
     if (!c->plan_valid || c->plan_track != 0 || c->plan_k != tile_qubits_for(c))
         return fail(PP_ERR_STATE, "the circuit's schedule is not on the device: evaluate it once with "
                                   "pp_evaluate (or serve it) after its last change");
@@ -1692,7 +1781,7 @@ extern "C" pp_status pp_evaluate_batch(pp_circuit *const *cs, int64_t count, voi
         std::vector<std::vector<int>> res_by_n(kResidentMaxN + 1);
         for (int64_t i = 0; i < count; ++i) {
             pp_circuit *c = cs[i];
-            if (c->engine != PP_ENGINE_DENSE || c->track) {
+            if (c->engine != PP_ENGINE_DENSE || c->track || c->ramp_gate >= 0) {  // evaluated one by one
                 B.single.push_back((int)i);
                 continue;
             }
@@ -1964,8 +2053,8 @@ extern "C" pp_status pp_evaluate_thetas(pp_circuit *c, int64_t count, const doub
     if (count > (1 << 20)) return fail(PP_ERR_INVALID, "at most 2^20 parameter sets per sweep");
     if (!c->have_gates) return fail(PP_ERR_STATE, "gates not loaded");
     if (!c->have_obs) return fail(PP_ERR_STATE, "observable not set");
-    if (c->engine != PP_ENGINE_DENSE || c->track)
-        return fail(PP_ERR_STATE, "parameter sweeps run on the DENSE engine without term tracking");
+    if (c->engine != PP_ENGINE_DENSE || c->track || c->ramp_opt)
+        return fail(PP_ERR_STATE, "parameter sweeps run on the DENSE engine without term tracking or frame ramp");
     hipStream_t s = (hipStream_t)stream;
     pp_status r = ensure_plan(c);
     if (r != PP_OK) return r;
@@ -2473,7 +2562,7 @@ pp_status after_theta(const pp_circuit *c, hipStream_t st) {
 // need none).
 pp_status prepare_request(ServedReq *r) {
     pp_circuit *c = r->c;
-    const bool dense_fast = c->engine == PP_ENGINE_DENSE && !c->track;
+    const bool dense_fast = c->engine == PP_ENGINE_DENSE && !c->track && !ramp_wanted(c);
     pp_status st = ensure_plan(c, !dense_fast);
     if (st != PP_OK) return st;
     fill_plan_stats(c);

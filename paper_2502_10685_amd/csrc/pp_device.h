@@ -273,6 +273,10 @@ hipError_t launch_frame_x0(FrameBuffers &f, int dtype_bytes, const uint64_t *xro
                            int ncodes, int npasses, SparseBuffers &out, hipStream_t s);
 // Every string in its actual form into out (x, z, weight in out's type),
 // count and overflow flag into out.count[0], [1].
+// The frame's strings after its last pass, in their actual form, into a
+// zeroed 4^n DENSE weight array (the ramp of a DENSE evaluation).
+hipError_t launch_frame_to_dense(FrameBuffers &f, int dtype_bytes, const uint32_t *codes, int ncodes, int npasses,
+                                 void *coef, hipStream_t s);
 hipError_t launch_frame_materialize(FrameBuffers &f, int dtype_bytes, const uint32_t *codes, int ncodes,
                                     int npasses, SparseBuffers &out, hipStream_t s);
 // list length after `npasses` passes (the counters of the last one)

@@ -899,6 +899,28 @@ __global__ __launch_bounds__(SP_BLOCK) void frame_materialize_kernel(FrameBuffer
     }
 }
 
+// The ramp of a DENSE evaluation: the frame engine's strings (after its
+// last pass), mapped through the frame's Clifford gates to their actual
+// form, written into the 4^n weight array (already zero) at slot
+// sum_q (x_q + 2 z_q) 4^q.  The list holds each string once, so plain
+// stores suffice.
+template <typename T>
+__global__ __launch_bounds__(SP_BLOCK) void frame_to_dense_kernel(FrameBuffers f, const uint32_t *__restrict__ codes,
+                                                                 int ncodes, int npasses, T *__restrict__ coef) {
+    const long long T0 = frame_len(f, npasses - 1);
+    const uint64_t lo = (1ull << f.n) - 1ull;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < T0; i += (long long)gridDim.x * blockDim.x) {
+        const uint64_t key = f.keys[i];
+        uint64_t x = key & lo, z = key >> f.n;
+        unsigned neg = 0;
+        clifford_apply(x, z, neg, codes, 0, ncodes);
+        long long slot = 0;
+        for (int q = 0; q < f.n; ++q) slot |= (long long)(((x >> q) & 1u) | (((z >> q) & 1u) << 1)) << (2 * q);
+        const double v = ldc<T>(f.coef, i);
+        coef[slot] = (T)(neg ? -v : v);
+    }
+}
+
 __global__ void zero_ll_kernel(long long *p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0;
@@ -1085,6 +1107,18 @@ hipError_t launch_frame_x0(FrameBuffers &f, int dtype_bytes, const uint64_t *xro
     else
         hipLaunchKernelGGL(frame_x0_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, f, xrows, codes, ncodes, npasses,
                            out.x, out.z, out.c, out.count);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_to_dense(FrameBuffers &f, int dtype_bytes, const uint32_t *codes, int ncodes, int npasses,
+                                 void *coef, hipStream_t s) {
+    const int g = frame_grid(f) * SP_ITEMS;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(frame_to_dense_kernel<double>, dim3(g), dim3(SP_BLOCK), 0, s, f, codes, ncodes, npasses,
+                           (double *)coef);
+    else
+        hipLaunchKernelGGL(frame_to_dense_kernel<float>, dim3(g), dim3(SP_BLOCK), 0, s, f, codes, ncodes, npasses,
+                           (float *)coef);
     return hipGetLastError();
 }
 
