@@ -315,6 +315,48 @@ def sparse_leg(api, torch, engines=("frame", "graph", "sortmerge")):
     return out
 
 
+def ramp_leg(api, torch):
+    """DENSE evaluations with and without the Clifford-frame ramp
+    (PP_OPT_FRAME_RAMP = 6: the frame runs the gates over which the set
+    stays below 4^n / 64): a random circuit (the set fills 4^n within a few
+    dozen rotations) and a Clifford-heavy one (5 % rotations, the set stays
+    small for most of the circuit), both n = 12."""
+    from paper_2502_10685_amd import workloads as W
+    rng = np.random.default_rng(12)
+    gates, p = W.random_gates(rng, 12, 4000)
+    ops = np.asarray(gates[0]).copy()
+    rot = ops >= 3
+    keep = ~rot | (rng.random(len(ops)) < 0.1)  # about 5 % rotations left
+    g2 = tuple(np.asarray(a)[keep] for a in gates)
+    # renumber the kept rotations' parameters
+    par = np.full(len(g2[0]), -1, np.int32)
+    rmask = g2[0] >= 3
+    par[rmask] = np.arange(int(rmask.sum()), dtype=np.int32)
+    cliff = W.make_circuit(12, (g2[0], g2[1], g2[2], par), int(rmask.sum()), W.obs_z(12, [0, 1]),
+                           rng.uniform(0, 2 * np.pi, int(rmask.sum())))
+    cases = [("random n=12 m=3000 seed 12", W.random_circuit(np.random.default_rng(12), 12, 3000, W.obs_z(12, [0, 1]))),
+             (f"Clifford-heavy n=12 m={cliff.m} ({int(rmask.sum())} rotations)", cliff)]
+    out = []
+    for name, wc in cases:
+        row = {"workload": name}
+        for ramp in (0, 6):
+            c = api.Circuit.from_workload(wc, engine="dense", frame_ramp=ramp)
+            c.evaluate()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                ev = c.evaluate()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 5
+            st = c.stats()
+            row["ramp" if ramp else "plain"] = {"ms": dt * 1e3, "passes": int(st["passes"]), "expval": float(ev.item())}
+            c.close()
+        row["speedup"] = row["plain"]["ms"] / row["ramp"]["ms"]
+        row["expval_abs_diff"] = abs(row["plain"]["expval"] - row["ramp"]["expval"])
+        out.append(row)
+    return out
+
+
 def density_leg(api, torch):
     """The paper's toDM task (rho = U|0><0|U^dag, pp_density_matrix) on its
     timing shape (n = 4, 60,200 gates: CX ring + RZ RX RZ blocks) and on a
@@ -715,6 +757,11 @@ def main():
             log(f"sparse {r['workload']}: {r['ms']:.2f} ms"
                 + (f" ({r['ms_graph']:.2f} ms as a graph)" if "ms_graph" in r else "")
                 + f", {r['final_terms']} strings, {r['updates_per_s']:.3e} updates/s")
+
+    if not args.no_sparse and args.workload == "batch512":
+        res["frame_ramp"] = ramp_leg(api, torch)
+        for r in res["frame_ramp"]:
+            log(f"frame ramp {r['workload']}: {r['plain']['ms']:.2f} ms plain, {r['ramp']['ms']:.2f} ms with the ramp")
 
     if not args.no_density and args.workload == "batch512":
         log("density matrix (toDM)")
