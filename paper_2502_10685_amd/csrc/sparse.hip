@@ -750,7 +750,7 @@ __global__ __launch_bounds__(SP_BLOCK) void frame_pass_kernel(FrameBuffers f, Fr
         // kept in flight side by side rather than one by one
         uint64_t key[SP_ITEMS], slot[SP_ITEMS], kc[SP_ITEMS];
         FrameSlot e[SP_ITEMS];
-        double vc[SP_ITEMS];
+        double vc[SP_ITEMS], cw[SP_ITEMS];
         unsigned anti = 0, kids = 0;
 #pragma unroll
         for (int it = 0; it < SP_ITEMS; ++it) {
@@ -760,9 +760,14 @@ __global__ __launch_bounds__(SP_BLOCK) void frame_pass_kernel(FrameBuffers f, Fr
             anti |= (unsigned)a << it;
             slot[it] = frame_home(key[it] ^ p.pmask, f.slot_bits);
         }
+        // the first probe and the weight of every anticommuting item, all
+        // in flight before any is used
 #pragma unroll
         for (int it = 0; it < SP_ITEMS; ++it)
-            if ((anti >> it) & 1u) e[it] = frame_slot(f, slot[it]);
+            if ((anti >> it) & 1u) {
+                e[it] = frame_slot(f, slot[it]);
+                cw[it] = ldc<T>(f.coef, t * SP_TILE + it * SP_BLOCK + threadIdx.x);
+            }
 #pragma unroll
         for (int it = 0; it < SP_ITEMS; ++it) {
             kc[it] = 0;
@@ -771,7 +776,7 @@ __global__ __launch_bounds__(SP_BLOCK) void frame_pass_kernel(FrameBuffers f, Fr
             const long long i = t * SP_TILE + it * SP_BLOCK + threadIdx.x;
             const uint64_t K = key[it] ^ p.pmask;
             const long long j = frame_resolve(f, K, slot[it], e[it]);
-            const double cS = ldc<T>(f.coef, i);
+            const double cS = cw[it];
             if (j < 0) {
                 stc<T>(f.coef, i, cS * cs);
                 kids |= 1u << it;
