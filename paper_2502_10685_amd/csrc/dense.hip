@@ -512,7 +512,7 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
             const int c = sw(((e & 3) << (2 * A)) | ((e >> 2) << (2 * B)));
             return *(LT *)(size_t)((svb ^ (unsigned)((c & 31) * (int)sizeof(T))) + (unsigned)((c & ~31) * (int)sizeof(T)));
         };
-        constexpr bool kShapes = NG >= 64 && sizeof(T) == 8;  // FP32 tiles keep the member loop (register budget)
+        constexpr bool kShapes = NG >= 64;
         double v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = (double)slot(e);
