@@ -497,9 +497,11 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
         const int lane = tid & 63;
         uint32_t wl = 0, ml = 0;  // word 0 and map index of member `lane`
         if constexpr (NG >= 64) {
-            const uint32_t *ow = reinterpret_cast<const uint32_t *>(&ops[first + (lane < cnt ? lane : 0)]);
-            wl = ow[0];
-            ml = ow[2];
+            if (shape == 0) {  // a shape's fields all came with its header
+                const uint32_t *ow = reinterpret_cast<const uint32_t *>(&ops[first + (lane < cnt ? lane : 0)]);
+                wl = ow[0];
+                ml = ow[2];
+            }
         }
         // Slot sv ^ c of the block, with c = cl | ch (cl the bits below 5,
         // ch the rest, which sv does not have): the tile starts on a 256-byte
