@@ -834,29 +834,34 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((BLOCK ==
 // tile (base = the tile's first slot), the lane's slot offset in a VGPR and
 // the register's in an SGPR, so the 64 accesses of a lane need no address
 // registers.  Both offsets are below 2^31 bytes when the tile's qubits are
-// all below 14 (the launcher only picks this kernel for n <= 14).
+// all below 14 (the launcher only picks this kernel for n <= 14).  Every
+// weight is read once and written once per pass, so both carry the
+// non-temporal hint (nt): the streamed array then does not push the op
+// lists and maps, which every tile re-reads, out of L2.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(void *p) {
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, -1, 0x00020000);
 }
+// cache-policy operand of the buffer builtins: bit 1 is nt on gfx950
+constexpr int kNonTemporal = 2;
 template <typename T>
 struct BufIO;
 template <>
 struct BufIO<double> {
     typedef unsigned V __attribute__((ext_vector_type(2)));
     static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, kNonTemporal));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double v) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, kNonTemporal);
     }
 };
 template <>
 struct BufIO<float> {
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, kNonTemporal));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, kNonTemporal);
     }
 };
 
@@ -955,10 +960,10 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
         for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
     }
     // Per tile: ops (unless the descriptor repeats), the next tile's early
-    // rows' loads, the ops in LDS, this tile's stores, then (FP64) the late
-    // rows' loads and the wait for all of them.  The early rows' wait does
-    // not cover the fresh stores; the late rows' does (one counter for both),
-    // which the fourth workgroup per CU hides.
+    // rows' loads, the ops in LDS, (FP64) the late rows' loads, this tile's
+    // stores, then the wait for the loads.  Loads and stores share one
+    // counter that completes in issue order, so with every load issued
+    // before the stores that wait does not cover the stores.
     const TilePassDesc *cached = nullptr;  // descriptor whose whole op list is in oc
     long long tcount = 0, updates = 0;
     for (;;) {
@@ -972,10 +977,10 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
         const bool has_next = nblk < total;
         TileLoc nxt = cur;
         // rows of the next tile loaded while the ops run: all of them in
-        // FP32; half in FP64, where the whole tile in registers would push
-        // the kernel past 128 VGPRs (three waves per SIMD instead of four,
-        // which cost 7 %); the other half is loaded after this tile's stores
-        constexpr int PE = sizeof(T) == 8 ? PER / 2 : PER;
+        // FP32; 12 of 16 in FP64, where more would push the kernel past 128
+        // VGPRs (three waves per SIMD instead of four, which cost 7 %) or
+        // spill; the other rows are loaded as soon as the ops end
+        constexpr int PE = sizeof(T) == 8 ? (PER * 12) / 16 : PER;
         if (has_next) {
             nxt = locate_tile<T, K, BLOCK>(descs, grp, nblk, tid);
             const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
@@ -986,6 +991,19 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
         run_ops<T, false, K, BLOCK, kStreamOps>(lc, nullptr, cur.d->ops, cur.d->maps, o0, o1, tcount, updates, redi, &oc,
                                                 true);
         if (!fits) cached = nullptr;  // run_ops reloaded later chunks into oc
+        if constexpr (PE < PER) {
+            if (has_next) {
+                const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
+                const uint64_t qubits = nxt.d->qubits;
+#pragma unroll
+                for (int r = PE; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
+            } else {
+                // a constant, not the previous rows: keeping those as the
+                // merge's other input would hold their registers across the ops
+#pragma unroll
+                for (int r = PE; r < PER; ++r) pre[r] = T(0);
+            }
+        }
         T out[PER];
         // an opaque copy of the slot base: the 16 tile addresses are
         // recomputed per tile (16 XORs) instead of living in 16 VGPRs
@@ -1001,12 +1019,6 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
             for (int r = 0; r < PER; ++r) BufIO<T>::st(rs, cur.voff, stream_soff<T, K, BLOCK>(qubits, r), out[r]);
         }
         if (!has_next) break;
-        if constexpr (PE < PER) {
-            const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
-            const uint64_t qubits = nxt.d->qubits;
-#pragma unroll
-            for (int r = PE; r < PER; ++r) pre[r] = BufIO<T>::ld(rs, nxt.voff, stream_soff<T, K, BLOCK>(qubits, r));
-        }
         lds_barrier();  // every thread has read this tile and is done with oc
         st = stid;
         __asm__ volatile("" : "+v"(st));
