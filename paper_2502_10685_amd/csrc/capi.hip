@@ -458,6 +458,7 @@ struct pp_circuit {
     int frame_opt = 1;           // PP_OPT_SPARSE_FRAME
     int ramp_opt = 0;            // PP_OPT_FRAME_RAMP (DENSE)
     int plan_ramp_opt = 0;       // the ramp setting the plan was built with
+    bool plan_seg = false;       // the plan has register segments (register-tile kernel selected)
     int64_t ramp_gate = -1;      // DENSE ramp: gates [ramp_gate, m) run in the Clifford frame
     pp::FrameBuffers fb{};
     pp::FramePlan fplan;
@@ -748,9 +749,13 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
     if (r != PP_OK) return r;
     const int k = c->engine == PP_ENGINE_DENSE ? tile_qubits_for(c) : 0;
     const bool frame = wants_frame(c);
+    // 6-qubit tiles are ordered into register segments only for the
+    // register-tile kernel; selecting it (or another kernel) re-plans
+    const int tv6 = pp::tile_kernel_variant(6);
+    const bool seg = c->engine == PP_ENGINE_DENSE && (tv6 == 3 || tv6 == 4);
     // the descriptors hold the weight pointer they were built with
     if (c->plan_valid && c->plan_track == c->track && c->plan_k == k && c->plan_coef == c->coef &&
-        c->plan_frame == frame && c->plan_ramp_opt == c->ramp_opt)
+        c->plan_frame == frame && c->plan_ramp_opt == c->ramp_opt && c->plan_seg == seg)
         return PP_OK;
     free_plan_buffers(c);
     if (c->track && c->engine == PP_ENGINE_DENSE && !c->pres) HIPCHK(dalloc(&c->pres, (size_t)dense_slots(c->n)));
@@ -784,16 +789,21 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
         if (c->ramp_gate >= 0) {
             pp::PlanOptions o;
             o.g_end = c->ramp_gate;  // the dense sweep takes the gates before the frame's
+            o.segments = seg;
             c->dplan = pp::plan_dense_opts(c->g, k, kLowQubits, o);
         } else {
-            c->dplan = pp::plan_dense(c->g, k, kLowQubits, c->track == 0, c->track == 0);
+            pp::PlanOptions o;
+            o.compose = o.group = o.reorder = c->track == 0;
+            o.segments = seg;
+            c->dplan = pp::plan_dense_opts(c->g, k, kLowQubits, o);
         }
         const pp::DensePlan &P = c->dplan;
         {
             // the kernels trust the schedule's digits and segment bounds
             const std::string bad = pp::plan_check(P, c->n);
             if (!bad.empty()) return fail(PP_ERR_STATE, "planner self-check: " + bad);
-            if (!c->track && !pp::plan_segmented(P)) return fail(PP_ERR_STATE, "planner self-check: unsegmented pass");
+            if (!c->track && seg && !pp::plan_segmented(P))
+                return fail(PP_ERR_STATE, "planner self-check: unsegmented pass");
         }
         if ((r = upload_vec(&c->d_ops, P.ops)) != PP_OK) return r;
         if ((r = upload_vec(&c->d_roff, P.roff)) != PP_OK) return r;
@@ -851,6 +861,7 @@ pp_status ensure_plan(pp_circuit *c, bool weights = true) {
     c->plan_coef = c->coef;
     c->plan_frame = frame;
     c->plan_ramp_opt = c->ramp_opt;
+    c->plan_seg = seg;
     c->plan_gen = ++g_plan_gen;
     return PP_OK;
 }

@@ -895,9 +895,13 @@ __device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ 
 #pragma unroll
     for (int j = 0; j < 8; ++j)
         if (j < K) inmask |= 1u << (unsigned)((qubits >> (8 * j)) & 0xff);
+    // the tile index's digits go to the qubits outside the tile, lowest
+    // first: one step per outside qubit
     long long base = 0, t = tile;
-    for (int q = 0; q < n; ++q) {
-        if ((inmask >> q) & 1u) continue;
+    unsigned out = ~inmask & ((1u << n) - 1u);
+    while (out) {
+        const int q = __builtin_ctz(out);
+        out &= out - 1u;
         base |= (t & 3ll) << (2 * q);
         t >>= 2;
     }
@@ -912,9 +916,16 @@ __device__ __forceinline__ TileLoc locate_tile(const TilePassDesc *__restrict__ 
     return TileLoc{d, base, voff * (unsigned)sizeof(T)};
 }
 
+// Byte offset (uniform) of row r of a thread's slots: the row supplies the
+// tile digits from 4 up; in 32 bits, with each digit value times the
+// element size a constant, so a row costs a shift per digit and an OR.
 template <typename T, int K, int BLOCK>
 __device__ __forceinline__ unsigned stream_soff(uint64_t qubits, int r) {
-    return (unsigned)deposit_digits(r * BLOCK, qubits, 4, K) * (unsigned)sizeof(T);
+    unsigned g = 0;
+#pragma unroll
+    for (int j = 4; j < K; ++j)
+        g |= ((((unsigned)(r * BLOCK) >> (2 * j)) & 3u) * (unsigned)sizeof(T)) << (2u * (unsigned)((qubits >> (8 * j)) & 0xff));
+    return g;
 }
 
 // 256 threads for tiles up to 4^6 slots (four workgroups per CU: at most 128

@@ -297,14 +297,14 @@ void split_waves(std::vector<DOp> &ops, DensePass &ps) {
     }
 }
 
-void group_all(DensePlan &P) {
+void group_all(DensePlan &P, bool segments) {
     int shift = 0;
     for (DensePass &ps : P.passes) {
         ps.op_begin += shift;
         ps.op_end += shift;
         const std::vector<DOp> in(P.ops.begin() + ps.op_begin, P.ops.begin() + ps.op_end);
         std::vector<DOp> out =
-            (!P.resident && ps.k == kSegTileDigits) ? segment_ops(in, ps.k) : group_ops(in, ps.k);
+            (segments && !P.resident && ps.k == kSegTileDigits) ? segment_ops(in, ps.k) : group_ops(in, ps.k);
         if (!P.resident && ps.k == 6) split_waves(out, ps);
         P.ops.erase(P.ops.begin() + ps.op_begin, P.ops.begin() + ps.op_end);
         P.ops.insert(P.ops.begin() + ps.op_begin, out.begin(), out.end());
@@ -320,7 +320,7 @@ static DensePlan plan_dense_core(const GateList &g, int k, int low, const PlanOp
 
 DensePlan plan_dense_opts(const GateList &g, int k, int low, const PlanOptions &o) {
     DensePlan P = plan_dense_core(g, k, low, o);
-    if (o.group && o.compose && !o.slot) group_all(P);
+    if (o.group && o.compose && !o.slot) group_all(P, o.segments);
     return P;
 }
 

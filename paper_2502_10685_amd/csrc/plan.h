@@ -72,6 +72,10 @@ struct PlanOptions {
     bool group = true;  // pack ops on a common digit pair into GROUP ops
     bool reorder = true;
     bool lookahead = true;  // grow a tile by the gate that unlocks the most gates
+    // order tiled passes of kSegTileDigits qubits into register segments
+    // (SEG headers, which the register-tile kernel needs); the LDS kernels
+    // skip SEG headers, so without segments they decode fewer ops
+    bool segments = true;
     bool forward = false;
     int64_t g_begin = 0, g_end = -1;
     const std::vector<int32_t> *slot = nullptr;

@@ -417,9 +417,13 @@ def test_resident_block_sizes_agree(api, n):
 @pytest.mark.parametrize("n", [8, 9, 10])
 def test_register_tile_kernel_bitwise(api, n, dtype):
     """The register-tile kernel (one wave per 4^6-slot tile, the tile held in
-    registers, LDS only between digit-triple segments) against the 256-thread
-    LDS kernel: same ops, same order, same FP32 rounding points, so every
-    weight is identical bit for bit; both match the state vector."""
+    registers, LDS only between digit-triple segments), persistent or not,
+    against the 256-thread LDS kernel.  Selecting it re-plans the circuit
+    with its ops ordered into segments; its two forms run the same ops in the
+    same order with the same FP32 rounding points, so their weights are
+    identical bit for bit.  The LDS kernel's plan packs commuting ops in
+    another order (other rounding): its weights agree within the tolerance;
+    all match the state vector."""
     from paper_2502_10685_amd import _lib as L
     rng = np.random.default_rng(660 + n)
     wc = W.random_circuit(rng, n, 1500, W.obs_tfim(n))
@@ -439,18 +443,26 @@ def test_register_tile_kernel_bitwise(api, n, dtype):
     finally:
         L.tune_set(L.PP_TUNE_TILE_KERNEL, 6, old)
     e0, x0, z0, c0 = res[0]
-    for e3, x3, z3, c3 in res[1:]:
-        assert e0 == e3
-        assert np.array_equal(x0, x3) and np.array_equal(z0, z3)
-        assert np.array_equal(c0.view(np.uint64), c3.view(np.uint64))
-    assert abs(e0 - sv) <= tol
+    e3, x3, z3, c3 = res[1]
+    e4, x4, z4, c4 = res[2]
+    assert e3 == e4
+    assert np.array_equal(x3, x4) and np.array_equal(z3, z4)
+    assert np.array_equal(c3.view(np.uint64), c4.view(np.uint64))
+    # the same weights up to rounding (a string whose weight cancels to
+    # exactly zero in one order may be reported by the other only)
+    w0 = {(int(a), int(b)): float(w) for a, b, w in zip(x0, z0, c0)}
+    w3 = {(int(a), int(b)): float(w) for a, b, w in zip(x3, z3, c3)}
+    assert max(abs(w0.get(key, 0.0) - w3.get(key, 0.0)) for key in set(w0) | set(w3)) <= tol
+    for e in (e0, e3):
+        assert abs(e - sv) <= tol
 
 
 @pytest.mark.parametrize("n", [14, 15])
 def test_register_tile_kernel_largest_registers(api, n):
     """n = 14 is the largest register the register-tile kernel takes (its
     buffer offsets reach 2^31 bytes at FP64); at n = 15 the launcher runs the
-    LDS kernel instead.  Both settings agree bit for bit and match the state
+    LDS kernel instead.  Its two forms agree bit for bit, the LDS kernel's
+    plan (another op order) within the tolerance; all match the state
     vector."""
     from paper_2502_10685_amd import _lib as L
     rng = np.random.default_rng(657 + n)
@@ -467,7 +479,9 @@ def test_register_tile_kernel_largest_registers(api, n):
             c.close()
     finally:
         L.tune_set(L.PP_TUNE_TILE_KERNEL, 6, old)
-    assert vals[0] == vals[1] == vals[2], vals
+    assert vals[1] == vals[2], vals
+    for v in vals:
+        assert abs(v - sv) <= TOL64, vals
     assert abs(vals[1] - sv) <= TOL64
 
 
