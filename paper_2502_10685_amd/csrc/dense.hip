@@ -515,15 +515,15 @@ __device__ __forceinline__ void group_sweep(T *lc, const DOp *ops, int first, in
             return *(LT *)(size_t)((svb ^ (unsigned)((c & 31) * (int)sizeof(T))) + (unsigned)((c & ~31) * (int)sizeof(T)));
         };
         constexpr bool kShapes = NG >= 64;
+        // a shape's first map: its index came with the header, so its
+        // scalar loads go out before the block's LDS reads
+        double m1[9];
+        if (kShapes && shape != 0) load_map(m1, (ConstMaps)gmaps + 9ull * map1);
         double v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = (double)slot(e);
         if constexpr (kShapes) {
             if (shape != 0) {
-                // the maps' indices came with the header: no LDS read before
-                // their scalar loads
-                double m1[9];
-                load_map(m1, (ConstMaps)gmaps + 9ull * map1);
                 const ConstMaps s2 = (ConstMaps)gmaps + 9ull * map2;
 #define PP_SHAPE_CASE(S_, LO_, CODE_)                                                                          \
     case S_:                                                                                                   \
@@ -588,13 +588,23 @@ __device__ __forceinline__ void group_apply(T *lc, int a, int b, const DOp *ops,
         if constexpr ((B_) < K)                                                                                    \
             group_sweep<T, K, BLOCK, (A_), (B_)>(lc, ops, first, cnt, tid, gops, gmaps, shape, map1, map2);        \
         return;
-    switch (a * 8 + b) {
-        PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
-        PP_GROUP_CASE(0, 6) PP_GROUP_CASE(1, 2) PP_GROUP_CASE(1, 3) PP_GROUP_CASE(1, 4) PP_GROUP_CASE(1, 5)
-        PP_GROUP_CASE(1, 6) PP_GROUP_CASE(2, 3) PP_GROUP_CASE(2, 4) PP_GROUP_CASE(2, 5) PP_GROUP_CASE(2, 6)
-        PP_GROUP_CASE(3, 4) PP_GROUP_CASE(3, 5) PP_GROUP_CASE(3, 6) PP_GROUP_CASE(4, 5) PP_GROUP_CASE(4, 6)
-        PP_GROUP_CASE(5, 6)
-    default: return;  // the planner emits GROUP headers with a < b < K only
+    if constexpr (K <= 6) {  // only the pairs that exist: a shallower branch tree
+        switch (a * 8 + b) {
+            PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
+            PP_GROUP_CASE(1, 2) PP_GROUP_CASE(1, 3) PP_GROUP_CASE(1, 4) PP_GROUP_CASE(1, 5)
+            PP_GROUP_CASE(2, 3) PP_GROUP_CASE(2, 4) PP_GROUP_CASE(2, 5)
+            PP_GROUP_CASE(3, 4) PP_GROUP_CASE(3, 5) PP_GROUP_CASE(4, 5)
+        default: return;  // the planner emits GROUP headers with a < b < K only
+        }
+    } else {
+        switch (a * 8 + b) {
+            PP_GROUP_CASE(0, 1) PP_GROUP_CASE(0, 2) PP_GROUP_CASE(0, 3) PP_GROUP_CASE(0, 4) PP_GROUP_CASE(0, 5)
+            PP_GROUP_CASE(0, 6) PP_GROUP_CASE(1, 2) PP_GROUP_CASE(1, 3) PP_GROUP_CASE(1, 4) PP_GROUP_CASE(1, 5)
+            PP_GROUP_CASE(1, 6) PP_GROUP_CASE(2, 3) PP_GROUP_CASE(2, 4) PP_GROUP_CASE(2, 5) PP_GROUP_CASE(2, 6)
+            PP_GROUP_CASE(3, 4) PP_GROUP_CASE(3, 5) PP_GROUP_CASE(3, 6) PP_GROUP_CASE(4, 5) PP_GROUP_CASE(4, 6)
+            PP_GROUP_CASE(5, 6)
+        default: return;  // the planner emits GROUP headers with a < b < K only
+        }
     }
 #undef PP_GROUP_CASE
 }
