@@ -546,6 +546,7 @@ def main():
                          "replayed as a hipGraph), 'sortmerge' (the sort-merge engine and the truncated run)")
     ap.add_argument("--no-density", action="store_true", help="skip the density-matrix (toDM) leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed batch leg")
+    ap.add_argument("--no-ramp", action="store_true", help="skip the frame-ramp leg (it runs with the SPARSE leg)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
                     help="time the tuning candidates on this device first (defaults are MI355X measurements)")
@@ -758,7 +759,7 @@ def main():
                 + (f" ({r['ms_graph']:.2f} ms as a graph)" if "ms_graph" in r else "")
                 + f", {r['final_terms']} strings, {r['updates_per_s']:.3e} updates/s")
 
-    if not args.no_sparse and args.workload == "batch512":
+    if not args.no_sparse and not args.no_ramp and args.workload == "batch512":
         res["frame_ramp"] = ramp_leg(api, torch)
         for r in res["frame_ramp"]:
             log(f"frame ramp {r['workload']}: {r['plain']['ms']:.2f} ms plain, {r['ramp']['ms']:.2f} ms with the ramp")
