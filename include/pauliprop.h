@@ -438,7 +438,10 @@ PP_API void pp_server_destroy(pp_server *s);
  *                        persistent, prefetching the next tile.  Variants
  *                        1, 3 and 4 serve launches whose circuits have
  *                        n <= 14 (32-bit buffer offsets); larger ones run
- *                        variant 0.
+ *                        variant 0.  Choosing 3 or 4 for k = 6, or leaving
+ *                        them, re-plans a circuit at its next evaluation:
+ *                        their schedules order each pass into register
+ *                        segments.
  *   PP_TUNE_RESIDENT_BLOCK: index = n (5..7), value = 256, 512 or 1024
  *                        threads for the LDS-resident kernel (untracked runs).
  *   PP_TUNE_SORT_SHAPE: index = capacity class of a SPARSE circuit's term
@@ -451,9 +454,10 @@ PP_API void pp_server_destroy(pp_server *s);
  *                        5 = 6 bits, 16 terms (64 threads).  Every shape is
  *                        a stable sort on the same key: same order, same
  *                        results.
- * The kernel variants give bit-identical results for a given tile size; k
- * changes how ops are packed and therefore the rounding, so a circuit keeps
- * the k of its schedule.  The resident block size changes the order of the
+ * Variants 0, 1 and 2 give bit-identical results for a given tile size, and
+ * so do 3 and 4; the two groups' schedules order commuting ops differently
+ * and agree up to rounding.  k changes how ops are packed and therefore the
+ * rounding, so a circuit keeps the k of its schedule.  The resident block size changes the order of the
  * final readout sum only. */
 typedef enum pp_tune_key {
     PP_TUNE_TILE_QUBITS = 0,

@@ -6,9 +6,10 @@ Results are cached as JSON keyed by the device name and weight dtype, and
 applied through pp_tune_set.
 
 Probes are seeded random circuits (50% H/S/CX, 50% RX/RY/RZ) evaluated in
-batches large enough to fill the GPU; every candidate gives bit-identical
-results for a fixed tile size, and a changed tile size only changes rounding
-(the schedule packs the same gates differently).
+batches large enough to fill the GPU.  For a fixed tile size the candidates
+agree bit for bit, except that the register-tile kernels (variants 3 and 4)
+run a schedule ordered into register segments, which changes only rounding;
+so does a changed tile size (the schedule packs the same gates differently).
 """
 from __future__ import annotations
 
