@@ -633,6 +633,24 @@ std::string plan_check(const DensePlan &P, int n) {
             if (d.a >= k || (d.kind == DOP_CX && (d.b >= k || d.a == d.b))) return "op digit outside the tile";
             if (d.kind == DOP_U1 && d.map >= (uint32_t)P.nmaps()) return "map index out of range";
         }
+        // a skipped workgroup barrier: only in 6-digit tiled passes, between
+        // two ops that both avoid digit 5, so never after a pass's last op
+        // (the streaming kernel reads the tile out after that barrier)
+        const DOp *prev = nullptr;
+        for (int i = ps.op_begin; i < ps.op_end;) {
+            const DOp &d = P.ops[i];
+            if (d.kind == DOP_SEG) {
+                ++i;
+                continue;
+            }
+            if (prev && (prev->perm & kSkipBarrier) && ((sweep_digits(d) >> 5) & 1u))
+                return "barrier skipped before an op on digit 5";
+            if ((d.perm & kSkipBarrier) && (P.resident || k != 6 || ((sweep_digits(d) >> 5) & 1u)))
+                return "barrier skipped after an op on digit 5";
+            prev = &d;
+            i += d.kind == DOP_GROUP ? 1 + d.ngates : 1;
+        }
+        if (prev && (prev->perm & kSkipBarrier)) return "barrier skipped after a pass's last op";
     }
     if (expect != (int)P.ops.size()) return "ops outside every pass";
     return "";
