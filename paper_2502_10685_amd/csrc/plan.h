@@ -71,7 +71,7 @@ struct PlanOptions {
     bool compose = true;
     bool group = true;  // pack ops on a common digit pair into GROUP ops
     bool reorder = true;
-    bool lookahead = true;  // grow a tile by the gate that unlocks the most gates
+    bool lookahead = true;  // grow a tile by the gate whose greedy completion of the tile takes the most gates
     // order tiled passes of kSegTileDigits qubits into register segments
     // (SEG headers, which the register-tile kernel needs); the LDS kernels
     // skip SEG headers, so without segments they decode fewer ops
