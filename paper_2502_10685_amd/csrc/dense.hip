@@ -987,6 +987,17 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
     // before the stores that wait does not cover the stores.
     const TilePassDesc *cached = nullptr;  // descriptor whose whole op list is in oc
     long long tcount = 0, updates = 0;
+    // FP64: the next tile's op list comes into registers (one 16-byte op
+    // per lane of wave 0) with its first rows and goes to oc after this
+    // tile's last barrier.  A workgroup's consecutive tiles lie gridDim.x
+    // apart, in other circuits' passes, so staging at the top of the loop
+    // put a global round trip before every tile's ops.  The maps are not
+    // copied: the streaming sweeps read them by scalar loads.  FP32 keeps
+    // its whole-tile prefetch instead (the op words would not fit beside it).
+    constexpr bool kOpPrefetch = sizeof(T) == 8;
+    typedef unsigned OpW __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) OpW *GOpW;
+    OpW opw = {0u, 0u, 0u, 0u};
     for (;;) {
         const int o0 = cur.d->op_begin, o1 = cur.d->op_end;
         const bool fits = o1 - o0 <= kStreamOps;
@@ -998,12 +1009,22 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
         const bool has_next = nblk < total;
         TileLoc nxt = cur;
         // rows of the next tile loaded while the ops run: all of them in
-        // FP32; 12 of 16 in FP64, where more would push the kernel past 128
-        // VGPRs (three waves per SIMD instead of four, which cost 7 %) or
-        // spill; the other rows are loaded as soon as the ops end
-        constexpr int PE = sizeof(T) == 8 ? (PER * 12) / 16 : PER;
+        // FP32; 10 of 16 in FP64, where more beside the op words would push
+        // the kernel past 128 VGPRs (three waves per SIMD instead of four,
+        // which cost 7 %) or spill; the other rows are loaded as soon as the
+        // ops end
+        constexpr int PE = sizeof(T) == 8 ? (PER * 10) / 16 : PER;
+        bool op_pref = false;  // opw holds the next tile's whole op list
+        int next_ops = 0;
         if (has_next) {
             nxt = locate_tile<T, K, BLOCK>(descs, grp, nblk, tid);
+            if constexpr (kOpPrefetch) {
+                const int n0 = nxt.d->op_begin;
+                next_ops = nxt.d->op_end - n0;
+                op_pref = nxt.d != cur.d && next_ops <= kStreamOps;
+                if (op_pref && tid < next_ops) opw = ((GOpW)nxt.d->ops)[n0 + tid];
+                else opw = OpW{0u, 0u, 0u, 0u};
+            }
             const __amdgpu_buffer_rsrc_t rs = tile_rsrc(reinterpret_cast<T *>(nxt.d->coef) + nxt.base);
             const uint64_t qubits = nxt.d->qubits;
 #pragma unroll
@@ -1041,6 +1062,10 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
         }
         if (!has_next) break;
         lds_barrier();  // every thread has read this tile and is done with oc
+        if (op_pref) {
+            if (tid < next_ops) reinterpret_cast<OpW *>(oc.ops)[tid] = opw;
+            cached = nxt.d;  // published by run_ops' first barrier
+        }
         st = stid;
         __asm__ volatile("" : "+v"(st));
 #pragma unroll
