@@ -454,6 +454,9 @@ PP_API void pp_server_destroy(pp_server *s);
  *                        5 = 6 bits, 16 terms (64 threads).  Every shape is
  *                        a stable sort on the same key: same order, same
  *                        results.
+ * The knobs are process-wide and not synchronized: set them while no
+ * evaluation, batch or server is running (a server's requests are planned
+ * on its preparation threads and launched later).
  * Variants 0, 1 and 2 give bit-identical results for a given tile size, and
  * so do 3 and 4; the two groups' schedules order commuting ops differently
  * and agree up to rounding.  k changes how ops are packed and therefore the
