@@ -980,9 +980,10 @@ void tile_stream_kernel(const TilePassDesc *__restrict__ descs, TileGroups grp) 
 #pragma unroll
         for (int r = 0; r < PER; ++r) lc[stid ^ sw(r * BLOCK)] = pre[r];
     }
-    // Per tile: ops (unless the descriptor repeats), the next tile's early
-    // rows' loads, the ops in LDS, (FP64) the late rows' loads, this tile's
-    // stores, then the wait for the loads.  Loads and stores share one
+    // Per tile: its op list staged (unless it is already in oc), the next
+    // tile's early rows' loads (FP64: and its op list), the ops in LDS,
+    // (FP64) the late rows' loads, this tile's stores, then the wait for the
+    // loads.  Loads and stores share one
     // counter that completes in issue order, so with every load issued
     // before the stores that wait does not cover the stores.
     const TilePassDesc *cached = nullptr;  // descriptor whose whole op list is in oc
